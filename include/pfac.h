@@ -1,0 +1,223 @@
+/*
+ * pfac.h -- C ABI of the MI355X (gfx950) failure-less Aho-Corasick matcher.
+ *
+ * Problem (paper, Section II): locate all occurrences of any of a finite set
+ * of keywords in a text.  The matcher uses the failure-less parallel form of
+ * Aho-Corasick that the paper evaluates on the GPU (Section II, Fig. 3 "N" and
+ * Fig. 5): every byte offset of the text starts its own walk of the Goto trie
+ * from the root, the walk stops at the first missing transition, and every
+ * keyword equal to T[o .. j] for a state passed by the walk from o is reported
+ * at offset o.  Unlike the PFAC variant the paper describes, keywords nested in
+ * longer ones ("sub patterns", Section II) are all reported, so the result is
+ *
+ *     R = { (o, p) : T[o .. o + |k_p|) == k_p },
+ *
+ * an unordered set of (start offset, keyword id) pairs.  Keyword ids are the
+ * input indices 0 .. n-1.  Bytes are raw unsigned 0..255, compared exactly.
+ *
+ * Memory: the library owns automata (device memory, freed by ac_free).  The
+ * caller owns every text and match buffer passed in; those are DEVICE
+ * pointers (e.g. torch tensors on the GPU).  Every function returning int or
+ * int64_t returns a negative AC_E* code on error and records a message for
+ * ac_last_error() in the calling thread.
+ *
+ * Streams: every GPU call is stream-ordered on the hipStream_t passed in
+ * (0 = the null stream).  Calls on different streams may run concurrently; an
+ * automaton is read-only after ac_build.  Two host threads must not drive the
+ * same stream at once.
+ */
+#ifndef PFAC_H
+#define PFAC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define AC_OK        0
+#define AC_EINVAL   (-1)  /* bad argument: empty keyword, n <= 0, NULL pointer  */
+#define AC_ENOMEM   (-2)  /* host or device allocation failed                   */
+#define AC_EHIP     (-3)  /* a HIP runtime call failed                          */
+#define AC_ENOTSUP  (-4)  /* option combination not supported                   */
+
+typedef struct ac_automaton ac_automaton;   /* device automaton, immutable     */
+typedef struct ac_plan ac_plan;             /* host-side build result          */
+
+/* ---- build ---------------------------------------------------------------- */
+typedef struct {
+    /* Upper bound on the bytes of dense transition rows.  States are numbered
+     * breadth first; the shallowest states whose rows fit get dense int32
+     * rows, deeper ones a compact child-list layout.  0 = 64 MiB. */
+    int64_t dense_budget_bytes;
+    /* 24-bit odd multiplier of the prefix hash used by the candidate filter;
+     * 0 = default.  Any value gives the same matches. */
+    uint32_t hash_multiplier;
+    int32_t reserved[7];
+} ac_build_opts;
+
+/*
+ * Build an automaton from n_patterns keywords (host memory: patterns[i] points
+ * at lengths[i] bytes).  Steps (paper Section II, Fig. 5): Goto trie over the
+ * keywords, breadth-first state numbering, Output lists (keyword ids per
+ * state), alphabet compression (byte -> class, unused bytes -> a dead class),
+ * dense/compact transition layout, candidate filter over each keyword's first
+ * min(3, shortest keyword) bytes, then one upload to the current device.
+ * Errors: AC_EINVAL (n_patterns <= 0, NULL pointer, empty keyword),
+ * AC_ENOMEM, AC_EHIP.  On success *out owns device memory until ac_free.
+ */
+int ac_build(const uint8_t *const *patterns, const int64_t *lengths, int32_t n_patterns,
+             const ac_build_opts *opts, ac_automaton **out);
+
+/* Same, with keywords packed as bytes[offsets[i] .. offsets[i+1]) (host). */
+int ac_build_csr(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns,
+                 const ac_build_opts *opts, ac_automaton **out);
+
+void ac_free(ac_automaton *a);
+
+/* ---- match ---------------------------------------------------------------- */
+typedef struct {
+    int64_t *offset;      /* device [capacity]: start offset of each match     */
+    int32_t *pattern_id;  /* device [capacity]: keyword id of each match       */
+    int64_t capacity;     /* entries available in both arrays                  */
+} ac_matches;
+
+/* Kernel choice; zero-initialise for the library's defaults. */
+#define AC_POLICY_AUTO      0
+#define AC_POLICY_FILTERED  1  /* prefix-filter every offset, walk candidates   */
+#define AC_POLICY_DIRECT    2  /* walk every offset from the root (plain PFAC)  */
+
+#define AC_FILTER_AUTO      0
+#define AC_FILTER_BYTES17   1  /* 2^17-entry byte map, 128 KiB of LDS           */
+#define AC_FILTER_BITS20    2  /* 2^20-bit map, 128 KiB of LDS                  */
+#define AC_FILTER_BYTES16   3  /* 2^16-entry byte map, 64 KiB of LDS            */
+#define AC_FILTER_BITS19    4  /* 2^19-bit map, 64 KiB of LDS                   */
+
+typedef struct {
+    int32_t policy;         /* AC_POLICY_*                                        */
+    int32_t filter;         /* AC_FILTER_* (FILTERED policy)                      */
+    int32_t block;          /* threads per block: 256, 512 or 1024; 0 = auto     */
+    int32_t segs;           /* 1 KiB segments per wave step: 1, 2 or 4; 0 = auto */
+    int32_t grid_per_cu;    /* resident blocks per compute unit; 0 = auto        */
+    int32_t table_in_lds;   /* DIRECT: -1/0 = auto, 1 = force LDS, 2 = global     */
+    int32_t reserved[6];
+} ac_launch;
+
+/*
+ * Match every occurrence in d_text[0 .. len) (device).  Writes up to
+ * matches->capacity (offset, pattern_id) pairs in unspecified order and
+ * returns the TRUE number of matches |R| (>= 0), also when it exceeds the
+ * capacity; then an unspecified subset of `capacity` matches is written and
+ * the caller may retry with a larger buffer.  matches == NULL counts only.
+ * len == 0 returns 0.  d_text may have any alignment.
+ * The call is stream-ordered on `stream` and synchronises it to return the
+ * count.  Errors: AC_EINVAL (NULL automaton, NULL text with len > 0, len < 0,
+ * capacity < 0, NULL arrays with capacity > 0), AC_EHIP.
+ */
+int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len,
+                 const ac_matches *matches, hipStream_t stream);
+
+/* ac_match with an explicit kernel choice (NULL = defaults). */
+int64_t ac_match_ex(const ac_automaton *a, const uint8_t *d_text, int64_t len,
+                    const ac_matches *matches, const ac_launch *launch, hipStream_t stream);
+
+/*
+ * Asynchronous form: enqueues the scan on `stream` and writes the match count
+ * to d_count (device int64) without synchronising; returns AC_OK or an error.
+ * It makes no allocation and no memset, so it may be captured in a HIP graph.
+ */
+int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len,
+                   const ac_matches *matches, const ac_launch *launch,
+                   int64_t *d_count, hipStream_t stream);
+
+/* ---- batches -------------------------------------------------------------- */
+typedef struct {
+    int32_t *text_id;         /* device [capacity]                              */
+    int64_t *offset;          /* device [capacity]: offset within its text      */
+    int32_t *pattern_id;      /* device [capacity]                              */
+    int64_t capacity;
+    int64_t *per_text_count;  /* device [n_texts] or NULL: matches per text     */
+} ac_batch_matches;
+
+/*
+ * Match n_texts texts packed back to back: text t is
+ * d_texts[d_text_offsets[t] - d_text_offsets[0] .. d_text_offsets[t+1] - d_text_offsets[0])
+ * where d_text_offsets (device int64[n_texts + 1], non-decreasing) is read by
+ * the kernel.  A match never spans two texts.  One launch scans the whole
+ * batch.  Returns the true total count as ac_match does; per_text_count, if
+ * given, receives exact per-text counts (it is cleared by the call).
+ * Errors: AC_EINVAL, AC_ENOTSUP (launch->policy == AC_POLICY_DIRECT), AC_EHIP.
+ */
+int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts,
+                       const int64_t *d_text_offsets, int32_t n_texts, int64_t total_bytes,
+                       const ac_batch_matches *matches, const ac_launch *launch,
+                       hipStream_t stream);
+
+/* Asynchronous, graph-capturable batch form (count to d_count, no sync). */
+int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts,
+                         const int64_t *d_text_offsets, int32_t n_texts, int64_t total_bytes,
+                         const ac_batch_matches *matches, const ac_launch *launch,
+                         int64_t *d_count, hipStream_t stream);
+
+/* ---- introspection ---------------------------------------------------------- */
+typedef struct {
+    int32_t n_patterns;
+    int32_t n_states;        /* trie states, root included                      */
+    int32_t n_classes;       /* alphabet classes (dense row width)              */
+    int32_t min_len, max_len;
+    int32_t prefix_len;      /* bytes hashed by the candidate filter            */
+    int32_t n_dense_states;  /* states [0, n_dense_states) have dense rows      */
+    int32_t dense_depth;     /* every state of depth <= dense_depth is dense    */
+    int32_t n_prefixes;      /* distinct keyword prefixes of prefix_len bytes   */
+    int32_t reserved0;
+    int64_t dense_bytes, compact_bytes, output_bytes, filter_bytes, device_bytes;
+    double build_ms;         /* host build + upload time                        */
+    int32_t reserved[8];
+} ac_info_t;
+
+int ac_info(const ac_automaton *a, ac_info_t *out);
+
+/* Kernel choice the library makes for a text of `len` bytes by default. */
+int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
+
+const char *ac_last_error(void);
+
+/* ---- host-side build, for inspection (no GPU needed) ------------------------ */
+/*
+ * ac_compile runs every host step of ac_build (trie, numbering, outputs,
+ * classes, layouts, filters) without touching a GPU.  ac_plan_info fills the
+ * same fields as ac_info (device_bytes = bytes ac_build would upload).
+ * ac_plan_export copies one table into host memory `dst` of `dst_bytes`
+ * and returns the bytes the table needs (call with dst = NULL to size it):
+ *   AC_TABLE_CLASS_MAP  uint8[256]         byte -> class
+ *   AC_TABLE_DENSE      int32[n_dense*C]   next state | final bit 31, 0 = dead
+ *   AC_TABLE_NODE       int32[2*(S-n_dense)] first child, child count | final bit 31
+ *   AC_TABLE_LABEL      uint8[S]           byte on the edge into each state
+ *   AC_TABLE_OUT_OFF    int32[S+1]         CSR offsets into AC_TABLE_OUT_PID
+ *   AC_TABLE_OUT_PID    int32[...]         keyword ids ending at each state
+ *   AC_TABLE_DEPTH      int32[S]           trie depth of each state
+ *   AC_TABLE_FILTER_*   filter maps (AC_FILTER_* + 100)
+ */
+#define AC_TABLE_CLASS_MAP  1
+#define AC_TABLE_DENSE      2
+#define AC_TABLE_NODE       3
+#define AC_TABLE_LABEL      4
+#define AC_TABLE_OUT_OFF    5
+#define AC_TABLE_OUT_PID    6
+#define AC_TABLE_DEPTH      7
+#define AC_TABLE_FILTER_BASE 100
+
+int ac_compile(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns,
+               const ac_build_opts *opts, ac_plan **out);
+int ac_plan_info(const ac_plan *p, ac_info_t *out);
+int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_bytes);
+/* Filter hash of a prefix value x (prefix bytes little-endian), as the kernel computes it. */
+uint32_t ac_plan_hash(const ac_plan *p, uint32_t x);
+void ac_plan_free(ac_plan *p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFAC_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) failure-less Aho-Corasick (PFAC) multi-pattern matcher.
+
+The matching runs in ``libpfac.so`` (HIP kernels behind the C ABI declared in
+``include/pfac.h``); this package only marshals arguments.  Importing it does
+not load the library; the first call does, and raises ``ImportError`` if the
+library was not built.
+"""
+
+from ._lib import (  # noqa: F401
+    AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT,
+    AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19,
+    EXPORTS, LIB_PATH, PfacError, load,
+)
+from .api import Automaton, Plan, launch_config, sorted_pairs  # noqa: F401

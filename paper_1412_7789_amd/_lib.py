@@ -1,0 +1,113 @@
+"""ctypes declarations of the C ABI in ``include/pfac.h`` (libpfac.so)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfac.so")
+
+AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_ENOTSUP = 0, -1, -2, -3, -4
+AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
+AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19 = 0, 1, 2, 3, 4
+AC_TABLE_CLASS_MAP, AC_TABLE_DENSE, AC_TABLE_NODE, AC_TABLE_LABEL = 1, 2, 3, 4
+AC_TABLE_OUT_OFF, AC_TABLE_OUT_PID, AC_TABLE_DEPTH, AC_TABLE_FILTER_BASE = 5, 6, 7, 100
+
+# every symbol include/pfac.h declares
+EXPORTS = [
+    "ac_build", "ac_build_csr", "ac_free", "ac_match", "ac_match_ex", "ac_match_async",
+    "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
+    "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
+    "ac_plan_free",
+]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("dense_budget_bytes", ctypes.c_int64), ("hash_multiplier", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class Matches(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_void_p), ("pattern_id", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class BatchMatches(ctypes.Structure):
+    _fields_ = [("text_id", ctypes.c_void_p), ("offset", ctypes.c_void_p), ("pattern_id", ctypes.c_void_p),
+                ("capacity", ctypes.c_int64), ("per_text_count", ctypes.c_void_p)]
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("filter", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("segs", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_patterns", ctypes.c_int32), ("n_states", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("min_len", ctypes.c_int32), ("max_len", ctypes.c_int32), ("prefix_len", ctypes.c_int32),
+                ("n_dense_states", ctypes.c_int32), ("dense_depth", ctypes.c_int32),
+                ("n_prefixes", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("dense_bytes", ctypes.c_int64), ("compact_bytes", ctypes.c_int64),
+                ("output_bytes", ctypes.c_int64), ("filter_bytes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 8)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpfac.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_1412_7789_amd.build, or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "ac_build": (ctypes.c_int, [vp, vp, i32, vp, vp]),
+        "ac_build_csr": (ctypes.c_int, [vp, vp, i32, vp, vp]),
+        "ac_free": (None, [vp]),
+        "ac_match": (i64, [vp, vp, i64, vp, vp]),
+        "ac_match_ex": (i64, [vp, vp, i64, vp, vp, vp]),
+        "ac_match_async": (ctypes.c_int, [vp, vp, i64, vp, vp, vp, vp]),
+        "ac_match_batch": (i64, [vp, vp, vp, i32, i64, vp, vp, vp]),
+        "ac_match_batch_async": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp, vp, vp]),
+        "ac_info": (ctypes.c_int, [vp, vp]),
+        "ac_default_launch": (ctypes.c_int, [vp, i64, vp]),
+        "ac_last_error": (ctypes.c_char_p, []),
+        "ac_compile": (ctypes.c_int, [vp, vp, i32, vp, vp]),
+        "ac_plan_info": (ctypes.c_int, [vp, vp]),
+        "ac_plan_export": (i64, [vp, i32, vp, i64]),
+        "ac_plan_hash": (u32, [vp, u32]),
+        "ac_plan_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PfacError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load().ac_last_error()
+        super().__init__(f"{where} failed ({code}): {msg.decode() if msg else ''}")
+        self.code = code
+
+
+def check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise PfacError(rc, where)
+    return rc

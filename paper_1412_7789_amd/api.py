@@ -1,0 +1,214 @@
+"""Python face of the C ABI: argument marshalling only.
+
+Every step of matching runs in the HIP library; PyTorch supplies device
+memory (tensors) and streams.  Functions raise ``PfacError`` on a negative
+return code and ``ImportError`` when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _csr(keywords: Sequence[bytes]) -> Tuple[np.ndarray, np.ndarray]:
+    lens = np.fromiter((len(k) for k in keywords), dtype=np.int64, count=len(keywords))
+    offs = np.zeros(len(keywords) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offs[1:])
+    flat = np.frombuffer(b"".join(keywords) or b"\0", dtype=np.uint8).copy()
+    return flat, offs
+
+
+def launch_config(policy: int = 0, filter: int = 0, block: int = 0, segs: int = 0,
+                  grid_per_cu: int = 0, table_in_lds: int = 0) -> L.Launch:
+    cfg = L.Launch()
+    cfg.policy, cfg.filter, cfg.block, cfg.segs = policy, filter, block, segs
+    cfg.grid_per_cu, cfg.table_in_lds = grid_per_cu, table_in_lds
+    return cfg
+
+
+def _opts(dense_budget_bytes: int, hash_multiplier: int) -> L.BuildOpts:
+    o = L.BuildOpts()
+    o.dense_budget_bytes = dense_budget_bytes
+    o.hash_multiplier = hash_multiplier
+    return o
+
+
+class Plan:
+    """Host-side build result (``ac_compile``): tables for inspection, no GPU."""
+
+    def __init__(self, keywords: Sequence[bytes], dense_budget_bytes: int = 0, hash_multiplier: int = 0):
+        lib = L.load()
+        flat, offs = _csr(keywords)
+        h = ctypes.c_void_p()
+        opts = _opts(dense_budget_bytes, hash_multiplier)
+        L.check(lib.ac_compile(flat.ctypes.data, offs.ctypes.data, len(keywords), ctypes.byref(opts),
+                               ctypes.byref(h)), "ac_compile")
+        self._h = h
+
+    def info(self) -> Dict[str, float]:
+        inf = L.Info()
+        L.check(L.load().ac_plan_info(self._h, ctypes.byref(inf)), "ac_plan_info")
+        return inf.as_dict()
+
+    def export(self, table: int, dtype) -> np.ndarray:
+        lib = L.load()
+        nbytes = L.check(lib.ac_plan_export(self._h, table, None, 0), "ac_plan_export")
+        out = np.empty(max(nbytes, 1), dtype=np.uint8)
+        L.check(lib.ac_plan_export(self._h, table, out.ctypes.data, out.size), "ac_plan_export")
+        return out[:nbytes].view(dtype)
+
+    def hash(self, x: int) -> int:
+        return int(L.load().ac_plan_hash(self._h, x & 0xFFFFFFFF))
+
+    def close(self) -> None:
+        if self._h:
+            L.load().ac_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Automaton:
+    """A keyword set built into a device automaton on the current GPU."""
+
+    def __init__(self, keywords: Sequence[bytes], dense_budget_bytes: int = 0, hash_multiplier: int = 0):
+        lib = L.load()
+        flat, offs = _csr(keywords)
+        h = ctypes.c_void_p()
+        opts = _opts(dense_budget_bytes, hash_multiplier)
+        L.check(lib.ac_build_csr(flat.ctypes.data, offs.ctypes.data, len(keywords), ctypes.byref(opts),
+                                 ctypes.byref(h)), "ac_build")
+        self._h = h
+        self.n_keywords = len(keywords)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def info(self) -> Dict[str, float]:
+        inf = L.Info()
+        L.check(L.load().ac_info(self._h, ctypes.byref(inf)), "ac_info")
+        return inf.as_dict()
+
+    def default_launch(self, n_bytes: int) -> Dict[str, int]:
+        cfg = L.Launch()
+        L.check(L.load().ac_default_launch(self._h, n_bytes, ctypes.byref(cfg)), "ac_default_launch")
+        return cfg.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            L.load().ac_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- single text -------------------------------------------------------------
+    def count(self, text, launch: Optional[L.Launch] = None, stream=None) -> int:
+        """Number of matches in a uint8 CUDA tensor (no match buffers)."""
+        _check_text(text)
+        return L.check(L.load().ac_match_ex(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(), None,
+                                            ctypes.byref(launch) if launch is not None else None,
+                                            _stream_ptr(stream)), "ac_match")
+
+    def match_into(self, text, offsets, pattern_ids, launch: Optional[L.Launch] = None, stream=None) -> int:
+        """Match into caller-owned int64/int32 CUDA tensors; returns the true count."""
+        _check_text(text)
+        m = L.Matches(ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(pattern_ids.data_ptr()),
+                      min(offsets.numel(), pattern_ids.numel()))
+        return L.check(L.load().ac_match_ex(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(),
+                                            ctypes.byref(m),
+                                            ctypes.byref(launch) if launch is not None else None,
+                                            _stream_ptr(stream)), "ac_match")
+
+    def match(self, text, capacity: Optional[int] = None, launch: Optional[L.Launch] = None, stream=None):
+        """All matches of a uint8 CUDA tensor as (offsets int64, pattern_ids int32)
+        CUDA tensors, unordered.  Retries once with an exact buffer if the first
+        guess was too small."""
+        import torch
+        cap = capacity if capacity is not None else max(1024, text.numel() // 512)
+        while True:
+            off = torch.empty(max(cap, 1), dtype=torch.int64, device=text.device)
+            pid = torch.empty(max(cap, 1), dtype=torch.int32, device=text.device)
+            n = self.match_into(text, off[:cap], pid[:cap], launch=launch, stream=stream)
+            if n <= cap:
+                return off[:n], pid[:n]
+            cap = n
+
+    def match_async(self, text, offsets, pattern_ids, d_count, launch: Optional[L.Launch] = None,
+                    stream=None) -> None:
+        """Enqueue only; the count lands in ``d_count`` (int64 CUDA tensor)."""
+        _check_text(text)
+        m = L.Matches(ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(pattern_ids.data_ptr()),
+                      min(offsets.numel(), pattern_ids.numel()))
+        L.check(L.load().ac_match_async(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(),
+                                        ctypes.byref(m),
+                                        ctypes.byref(launch) if launch is not None else None,
+                                        ctypes.c_void_p(d_count.data_ptr()), _stream_ptr(stream)),
+                "ac_match_async")
+
+    # -- batches -----------------------------------------------------------------
+    def match_batch_into(self, texts, text_offsets, text_ids, offsets, pattern_ids, per_text=None,
+                         launch: Optional[L.Launch] = None, stream=None, total_bytes: Optional[int] = None) -> int:
+        _check_text(texts)
+        n_texts = text_offsets.numel() - 1
+        total = texts.numel() if total_bytes is None else total_bytes
+        cap = min(offsets.numel(), pattern_ids.numel(), text_ids.numel())
+        m = L.BatchMatches(ctypes.c_void_p(text_ids.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                           ctypes.c_void_p(pattern_ids.data_ptr()), cap,
+                           ctypes.c_void_p(per_text.data_ptr()) if per_text is not None else None)
+        return L.check(L.load().ac_match_batch(self._h, ctypes.c_void_p(texts.data_ptr()),
+                                               ctypes.c_void_p(text_offsets.data_ptr()), n_texts, total,
+                                               ctypes.byref(m),
+                                               ctypes.byref(launch) if launch is not None else None,
+                                               _stream_ptr(stream)), "ac_match_batch")
+
+    def match_batch(self, texts, text_offsets, capacity: Optional[int] = None,
+                    launch: Optional[L.Launch] = None, stream=None):
+        """Match a packed batch; returns (text_ids, offsets, pattern_ids, per_text_count)."""
+        import torch
+        n_texts = text_offsets.numel() - 1
+        cap = capacity if capacity is not None else max(1024, texts.numel() // 512)
+        while True:
+            dev = texts.device
+            tid = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            off = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+            pid = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            per = torch.empty(max(n_texts, 1), dtype=torch.int64, device=dev)
+            n = self.match_batch_into(texts, text_offsets, tid[:cap], off[:cap], pid[:cap], per,
+                                      launch=launch, stream=stream)
+            if n <= cap:
+                return tid[:n], off[:n], pid[:n], per[:n_texts]
+            cap = n
+
+
+def _check_text(t) -> None:
+    import torch
+    if t.dtype != torch.uint8 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("text must be a contiguous uint8 CUDA tensor")
+
+
+def sorted_pairs(offsets, pattern_ids) -> Tuple[np.ndarray, np.ndarray]:
+    """Host copy of a match set sorted by (offset, id), for comparisons."""
+    off = offsets.cpu().numpy().astype(np.int64)
+    pid = pattern_ids.cpu().numpy().astype(np.int32)
+    order = np.lexsort((pid, off))
+    return off[order], pid[order]

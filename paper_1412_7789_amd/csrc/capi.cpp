@@ -1,0 +1,430 @@
+// C ABI of the failure-less Aho-Corasick matcher: argument checks, device
+// upload of a built automaton, per-stream count buffers, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+
+#include "pfac_internal.hpp"
+
+using namespace pfac;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(const char *what, hipError_t e) {
+    return fail(AC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// One device count word and one pinned host word per (device, stream),
+// allocated on first use and kept for the life of the process.
+struct CountSlot {
+    unsigned long long *d = nullptr;
+    unsigned long long *h = nullptr;
+};
+std::mutex g_slots_mu;
+std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
+
+int count_slot(int device, hipStream_t stream, CountSlot &out) {
+    std::lock_guard<std::mutex> lk(g_slots_mu);
+    auto key = std::make_pair(device, stream);
+    auto it = g_slots.find(key);
+    if (it != g_slots.end()) { out = it->second; return AC_OK; }
+    CountSlot s;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), sizeof(unsigned long long));
+    if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
+    e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
+    g_slots[key] = s;
+    out = s;
+    return AC_OK;
+}
+
+int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
+
+int upload(ac_automaton *a) {
+    const Plan &P = a->host;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    a->device = dev;
+    int cus = 0, lds = 0, lds_optin = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail("hipDeviceGetAttribute(cu)", e);
+    if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+        return hip_fail("hipDeviceGetAttribute(lds)", e);
+    if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) {
+        lds_optin = 0;
+        (void)hipGetLastError();
+    }
+    int lds_cu = 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
+        lds_cu = 0;
+        (void)hipGetLastError();
+    }
+    a->cu_count = std::max(1, cus);
+    a->lds_per_block = std::max(lds, lds_optin);
+    a->lds_per_cu = std::max<int64_t>(lds_cu, a->lds_per_block);
+
+    // section layout (each section 256-byte aligned and padded)
+    struct Sec { const void *src; int64_t bytes; int64_t at; };
+    Sec cls{P.cls, 256, 0};
+    Sec filt[kNumFilters];
+    Sec dense{P.dense.data(), int64_t(P.dense.size()) * 4, 0};
+    Sec node{P.node.data(), int64_t(P.node.size()) * 4, 0};
+    Sec label{P.label.data(), int64_t(P.label.size()), 0};
+    Sec ooff{P.out_off.data(), int64_t(P.out_off.size()) * 4, 0};
+    Sec opid{P.out_pid.data(), int64_t(P.out_pid.size()) * 4, 0};
+    int64_t at = 0;
+    auto place = [&](Sec &s) { s.at = at; at += pad256(std::max<int64_t>(s.bytes, 1)); };
+    place(cls);
+    for (int k = 0; k < kNumFilters; ++k) {
+        filt[k] = Sec{P.filter[k].data(), int64_t(P.filter[k].size()), 0};
+        place(filt[k]);
+    }
+    place(dense); place(node); place(label); place(ooff); place(opid);
+    a->dbytes = at;
+    std::vector<uint8_t> staging(size_t(at), 0);
+    auto copy = [&](const Sec &s) { if (s.bytes) std::memcpy(staging.data() + s.at, s.src, size_t(s.bytes)); };
+    copy(cls); for (auto &f : filt) copy(f); copy(dense); copy(node); copy(label); copy(ooff); copy(opid);
+    e = hipMalloc(&a->dmem, size_t(at));
+    if (e != hipSuccess) { a->dmem = nullptr; return fail(AC_ENOMEM, std::string("hipMalloc(automaton): ") + hipGetErrorString(e)); }
+    e = hipMemcpy(a->dmem, staging.data(), size_t(at), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail("hipMemcpy(automaton)", e);
+    uint8_t *b = static_cast<uint8_t *>(a->dmem);
+    DevAut &D = a->dev;
+    D.cls = b + cls.at;
+    for (int k = 0; k < kNumFilters; ++k) D.filter[k] = b + filt[k].at;
+    D.dense = reinterpret_cast<const int32_t *>(b + dense.at);
+    D.node = reinterpret_cast<const int32_t *>(b + node.at);
+    D.label = b + label.at;
+    D.out_off = reinterpret_cast<const int32_t *>(b + ooff.at);
+    D.out_pid = reinterpret_cast<const int32_t *>(b + opid.at);
+    D.C = P.C;
+    D.S = P.S;
+    D.S_dense = P.S_dense;
+    D.K = P.K;
+    D.max_len = P.max_len;
+    D.hash_mul = P.hash_mul;
+    return AC_OK;
+}
+
+void fill_info(const Plan &P, ac_info_t *o) {
+    std::memset(o, 0, sizeof(*o));
+    o->n_patterns = P.n_patterns;
+    o->n_states = P.S;
+    o->n_classes = P.C;
+    o->min_len = P.min_len;
+    o->max_len = P.max_len;
+    o->prefix_len = P.K;
+    o->n_dense_states = P.S_dense;
+    o->dense_depth = P.dense_depth;
+    o->n_prefixes = P.n_prefixes;
+    o->dense_bytes = int64_t(P.dense.size()) * 4;
+    o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
+    o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;
+    for (const auto &f : P.filter) o->filter_bytes += int64_t(f.size());
+    o->device_bytes = 256 + o->dense_bytes + o->compact_bytes + o->output_bytes + o->filter_bytes;
+    o->build_ms = P.build_ms;
+}
+
+int check_launch(const ac_launch *l) {
+    if (!l) return AC_OK;
+    if (l->policy < AC_POLICY_AUTO || l->policy > AC_POLICY_DIRECT) return fail(AC_EINVAL, "ac_launch: bad policy");
+    if (l->filter < AC_FILTER_AUTO || l->filter > AC_FILTER_BITS19) return fail(AC_EINVAL, "ac_launch: bad filter");
+    if (l->block != 0 && l->block != 256 && l->block != 512 && l->block != 1024)
+        return fail(AC_EINVAL, "ac_launch: block must be 256, 512 or 1024");
+    if (l->segs != 0 && l->segs != 1 && l->segs != 2 && l->segs != 4)
+        return fail(AC_EINVAL, "ac_launch: segs must be 1, 2 or 4");
+    if (l->grid_per_cu < 0 || l->grid_per_cu > 64) return fail(AC_EINVAL, "ac_launch: bad grid_per_cu");
+    return AC_OK;
+}
+
+int device_matches(const ac_automaton *a) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    if (dev != a->device) return fail(AC_EINVAL, "automaton was built on another device than the current one");
+    return AC_OK;
+}
+
+// Enqueue zero + scan for one text or a batch.
+int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch,
+            unsigned long long *d_count, hipStream_t stream) {
+    ac_launch cfg{};
+    if (launch) cfg = *launch;
+    if (batch && cfg.policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
+    resolve_launch(a, S.n, batch, cfg);
+    S.count = d_count;
+    std::string err;
+    int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
+    if (rc) return fail(rc, err);
+    rc = launch_scan(a, S, cfg, stream, err);
+    if (rc) return fail(rc, err);
+    return AC_OK;
+}
+
+int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch, hipStream_t stream) {
+    CountSlot slot;
+    int rc = count_slot(a->device, stream, slot);
+    if (rc) return rc;
+    rc = enqueue(a, S, launch, batch, slot.d, stream);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(slot.h, slot.d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    return int64_t(*slot.h);
+}
+
+int check_single(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *m) {
+    if (!a) return fail(AC_EINVAL, "ac_match: NULL automaton");
+    if (len < 0) return fail(AC_EINVAL, "ac_match: negative length");
+    if (len > 0 && !d_text) return fail(AC_EINVAL, "ac_match: NULL text");
+    if (m) {
+        if (m->capacity < 0) return fail(AC_EINVAL, "ac_match: negative capacity");
+        if (m->capacity > 0 && (!m->offset || !m->pattern_id)) return fail(AC_EINVAL, "ac_match: NULL match arrays");
+    }
+    return device_matches(a);
+}
+
+ScanArgs single_args(const uint8_t *d_text, int64_t len, const ac_matches *m) {
+    ScanArgs S{};
+    S.text = d_text;
+    S.n = len;
+    if (m && m->capacity > 0) {
+        S.out_off = m->offset;
+        S.out_pid = m->pattern_id;
+        S.cap = m->capacity;
+    }
+    return S;
+}
+
+int check_batch(const ac_automaton *a, const uint8_t *d_texts, const int64_t *d_off, int32_t n_texts,
+                int64_t total, const ac_batch_matches *m) {
+    if (!a) return fail(AC_EINVAL, "ac_match_batch: NULL automaton");
+    if (n_texts < 0) return fail(AC_EINVAL, "ac_match_batch: negative text count");
+    if (total < 0) return fail(AC_EINVAL, "ac_match_batch: negative total bytes");
+    if (n_texts > 0 && !d_off) return fail(AC_EINVAL, "ac_match_batch: NULL offsets");
+    if (total > 0 && !d_texts) return fail(AC_EINVAL, "ac_match_batch: NULL texts");
+    if (m) {
+        if (m->capacity < 0) return fail(AC_EINVAL, "ac_match_batch: negative capacity");
+        if (m->capacity > 0 && (!m->offset || !m->pattern_id || !m->text_id))
+            return fail(AC_EINVAL, "ac_match_batch: NULL match arrays");
+    }
+    return device_matches(a);
+}
+
+ScanArgs batch_args(const uint8_t *d_texts, const int64_t *d_off, int32_t n_texts, int64_t total,
+                    const ac_batch_matches *m) {
+    ScanArgs S{};
+    S.text = d_texts;
+    S.n = n_texts > 0 ? total : 0;
+    S.text_off = d_off;
+    S.n_texts = n_texts;
+    if (m) {
+        if (m->capacity > 0) {
+            S.out_off = m->offset;
+            S.out_pid = m->pattern_id;
+            S.out_tid = m->text_id;
+            S.cap = m->capacity;
+        }
+        S.per_text = m->per_text_count;
+    }
+    return S;
+}
+
+int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const ac_build_opts *opts,
+                 ac_automaton **out) {
+    if (!out) return fail(AC_EINVAL, "ac_build: NULL output pointer");
+    *out = nullptr;
+    auto t0 = std::chrono::steady_clock::now();
+    ac_automaton *a = new (std::nothrow) ac_automaton();
+    if (!a) return fail(AC_ENOMEM, "ac_build: out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = compile_plan(bytes, offsets, n, opts, a->host, err);
+    } catch (const std::bad_alloc &) {
+        rc = AC_ENOMEM;
+        err = "ac_build: out of host memory";
+    }
+    if (rc) { delete a; return fail(rc, err); }
+    rc = upload(a);
+    if (rc) { if (a->dmem) (void)hipFree(a->dmem); delete a; return rc; }
+    a->host.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = a;
+    return AC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ac_last_error(void) { return g_err.c_str(); }
+
+int ac_build_csr(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns, const ac_build_opts *opts,
+                 ac_automaton **out) {
+    return build_common(bytes, offsets, n_patterns, opts, out);
+}
+
+int ac_build(const uint8_t *const *patterns, const int64_t *lengths, int32_t n_patterns,
+             const ac_build_opts *opts, ac_automaton **out) {
+    if (n_patterns <= 0) return fail(AC_EINVAL, "ac_build: need at least one keyword");
+    if (!patterns || !lengths) return fail(AC_EINVAL, "ac_build: NULL keyword arrays");
+    std::vector<int64_t> offs(size_t(n_patterns) + 1, 0);
+    for (int32_t i = 0; i < n_patterns; ++i) {
+        if (lengths[i] <= 0) return fail(AC_EINVAL, "ac_build: keyword " + std::to_string(i) + " is empty");
+        if (!patterns[i]) return fail(AC_EINVAL, "ac_build: NULL keyword pointer");
+        offs[size_t(i) + 1] = offs[size_t(i)] + lengths[i];
+    }
+    std::vector<uint8_t> flat;
+    try {
+        flat.resize(size_t(offs.back()));
+    } catch (const std::bad_alloc &) {
+        return fail(AC_ENOMEM, "ac_build: out of host memory");
+    }
+    for (int32_t i = 0; i < n_patterns; ++i)
+        std::memcpy(flat.data() + offs[size_t(i)], patterns[i], size_t(lengths[i]));
+    return build_common(flat.data(), offs.data(), n_patterns, opts, out);
+}
+
+void ac_free(ac_automaton *a) {
+    if (!a) return;
+    if (a->dmem) (void)hipFree(a->dmem);
+    delete a;
+}
+
+int ac_info(const ac_automaton *a, ac_info_t *out) {
+    if (!a || !out) return fail(AC_EINVAL, "ac_info: NULL argument");
+    fill_info(a->host, out);
+    out->device_bytes = a->dbytes;
+    return AC_OK;
+}
+
+int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out) {
+    if (!a || !out) return fail(AC_EINVAL, "ac_default_launch: NULL argument");
+    std::memset(out, 0, sizeof(*out));
+    resolve_launch(a, len, false, *out);
+    return AC_OK;
+}
+
+int64_t ac_match_ex(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,
+                    const ac_launch *launch, hipStream_t stream) {
+    int rc = check_single(a, d_text, len, matches);
+    if (rc) return rc;
+    if ((rc = check_launch(launch))) return rc;
+    return sync_count(a, single_args(d_text, len, matches), launch, false, stream);
+}
+
+int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,
+                 hipStream_t stream) {
+    return ac_match_ex(a, d_text, len, matches, nullptr, stream);
+}
+
+int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,
+                   const ac_launch *launch, int64_t *d_count, hipStream_t stream) {
+    int rc = check_single(a, d_text, len, matches);
+    if (rc) return rc;
+    if ((rc = check_launch(launch))) return rc;
+    if (!d_count) return fail(AC_EINVAL, "ac_match_async: NULL count pointer");
+    return enqueue(a, single_args(d_text, len, matches), launch, false,
+                   reinterpret_cast<unsigned long long *>(d_count), stream);
+}
+
+int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets,
+                       int32_t n_texts, int64_t total_bytes, const ac_batch_matches *matches,
+                       const ac_launch *launch, hipStream_t stream) {
+    int rc = check_batch(a, d_texts, d_text_offsets, n_texts, total_bytes, matches);
+    if (rc) return rc;
+    if ((rc = check_launch(launch))) return rc;
+    return sync_count(a, batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches), launch, true,
+                      stream);
+}
+
+int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets,
+                         int32_t n_texts, int64_t total_bytes, const ac_batch_matches *matches,
+                         const ac_launch *launch, int64_t *d_count, hipStream_t stream) {
+    int rc = check_batch(a, d_texts, d_text_offsets, n_texts, total_bytes, matches);
+    if (rc) return rc;
+    if ((rc = check_launch(launch))) return rc;
+    if (!d_count) return fail(AC_EINVAL, "ac_match_batch_async: NULL count pointer");
+    return enqueue(a, batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches), launch, true,
+                   reinterpret_cast<unsigned long long *>(d_count), stream);
+}
+
+// ---- host-side inspection -----------------------------------------------------
+int ac_compile(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns, const ac_build_opts *opts,
+               ac_plan **out) {
+    if (!out) return fail(AC_EINVAL, "ac_compile: NULL output pointer");
+    *out = nullptr;
+    ac_plan *p = new (std::nothrow) ac_plan();
+    if (!p) return fail(AC_ENOMEM, "ac_compile: out of host memory");
+    std::string err;
+    int rc;
+    try {
+        rc = compile_plan(bytes, offsets, n_patterns, opts, p->p, err);
+    } catch (const std::bad_alloc &) {
+        rc = AC_ENOMEM;
+        err = "ac_compile: out of host memory";
+    }
+    if (rc) { delete p; return fail(rc, err); }
+    *out = p;
+    return AC_OK;
+}
+
+int ac_plan_info(const ac_plan *p, ac_info_t *out) {
+    if (!p || !out) return fail(AC_EINVAL, "ac_plan_info: NULL argument");
+    fill_info(p->p, out);
+    return AC_OK;
+}
+
+int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_bytes) {
+    if (!p) return fail(AC_EINVAL, "ac_plan_export: NULL plan");
+    const Plan &P = p->p;
+    const void *src = nullptr;
+    int64_t bytes = 0;
+    switch (table) {
+        case AC_TABLE_CLASS_MAP: src = P.cls; bytes = 256; break;
+        case AC_TABLE_DENSE: src = P.dense.data(); bytes = int64_t(P.dense.size()) * 4; break;
+        case AC_TABLE_NODE: src = P.node.data(); bytes = int64_t(P.node.size()) * 4; break;
+        case AC_TABLE_LABEL: src = P.label.data(); bytes = int64_t(P.label.size()); break;
+        case AC_TABLE_OUT_OFF: src = P.out_off.data(); bytes = int64_t(P.out_off.size()) * 4; break;
+        case AC_TABLE_OUT_PID: src = P.out_pid.data(); bytes = int64_t(P.out_pid.size()) * 4; break;
+        case AC_TABLE_DEPTH: src = P.depth.data(); bytes = int64_t(P.depth.size()) * 4; break;
+        default:
+            if (table > AC_TABLE_FILTER_BASE && table <= AC_TABLE_FILTER_BASE + kNumFilters) {
+                const auto &f = P.filter[table - AC_TABLE_FILTER_BASE - 1];
+                src = f.data();
+                bytes = int64_t(f.size());
+                break;
+            }
+            return fail(AC_EINVAL, "ac_plan_export: unknown table");
+    }
+    if (!dst) return bytes;
+    if (dst_bytes < bytes) return fail(AC_EINVAL, "ac_plan_export: destination too small");
+    if (bytes) std::memcpy(dst, src, size_t(bytes));
+    return bytes;
+}
+
+uint32_t ac_plan_hash(const ac_plan *p, uint32_t x) {
+    if (!p) return 0;
+    const uint32_t kmask = p->p.K >= 3 ? 0xFFFFFFu : ((1u << (8 * p->p.K)) - 1u);
+    return prefix_hash(x & kmask, p->p.hash_mul);
+}
+
+void ac_plan_free(ac_plan *p) { delete p; }
+
+}  // extern "C"

@@ -1,0 +1,487 @@
+// HIP kernels (gfx950) of the failure-less Aho-Corasick matcher.
+//
+// The method (paper, Section II; Fig. 3 "N", Fig. 5): every byte offset o of
+// the text starts a walk of the Goto trie at the root, follows T[o], T[o+1],
+// ... while transitions exist, and reports every keyword whose state it
+// enters.  No failure links are used.  Two kernels compute it:
+//
+// filtered_kernel (default).  A wave owns a 1-4 KiB chunk of text per step:
+//   each lane holds 16 contiguous bytes per 1 KiB segment in VGPRs (one
+//   coalesced 16-byte load; the 2-byte halo comes from the next lane), and
+//   for each of its 16 offsets tests the first K = min(3, shortest keyword)
+//   bytes against a hashed filter of the keywords' K-byte prefixes held in
+//   LDS.  An offset whose prefix is not in the filter cannot start a keyword
+//   (its walk dies within K steps without reaching a final state), so only
+//   the rare candidate offsets are queued (wave ballot + prefix count into a
+//   per-wave LDS queue) and walked, 64 at a time, through the transition
+//   table in global memory (L2-resident rows; dense rows for shallow states,
+//   compact child lists for deep ones).
+//
+// direct_kernel (plain PFAC).  A block stages its text tile plus a halo of
+//   (longest keyword - 1) bytes in LDS and walks every offset from the root
+//   through the dense table, itself in LDS when it fits.
+//
+// Both emit matches with a wave ballot: one atomic per wave reserves output
+// slots, each lane writes at its rank.  The returned count is exact even when
+// the output buffer is too small (only `cap` entries are written).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <mutex>
+
+#include "pfac_internal.hpp"
+
+namespace pfac {
+
+namespace {
+
+constexpr int kQueueCap = 128;   // per-wave candidate queue (entries)
+constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
+
+__device__ __forceinline__ unsigned lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ unsigned rank_in(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi(unsigned(mask >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(mask), 0u));
+}
+
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int lane) {
+    unsigned lo = __builtin_amdgcn_readlane(unsigned(v), lane);
+    unsigned hi = __builtin_amdgcn_readlane(unsigned(v >> 32), lane);
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+
+// Loads through an explicit global-address-space pointer: pointers taken out
+// of a by-value struct otherwise lower to flat loads, which also occupy the
+// LDS counter and would serialise with the filter lookups.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 global_u32x4;
+typedef const __attribute__((address_space(1))) uint32_t global_u32;
+
+__device__ __forceinline__ u32x4 gload16(const uint8_t *p) { return *(global_u32x4 *)(p); }
+__device__ __forceinline__ uint32_t gload4(const uint8_t *p) { return *(global_u32 *)(p); }
+
+// Orders LDS traffic between lanes of one wave (queue producer -> consumer).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Reports every keyword id of final state s at `off` (relative to its text).
+// Called from divergent code: the lanes calling it together share one atomic
+// per round; lanes with more ids loop more rounds.
+__device__ void emit(const DevAut &A, const ScanArgs &S, int64_t off, int32_t tid, int32_t s) {
+    const int32_t k0 = A.out_off[s], k1 = A.out_off[s + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+        const unsigned long long act = __ballot(1);
+        const unsigned rank = rank_in(act);
+        const int leader = __ffsll(static_cast<long long>(act)) - 1;
+        unsigned long long base = 0;
+        if (rank == 0) base = atomicAdd(S.count, static_cast<unsigned long long>(__popcll(act)));
+        base = readlane64(base, leader);
+        const unsigned long long idx = base + rank;
+        if (idx < static_cast<unsigned long long>(S.cap)) {
+            S.out_off[idx] = off;
+            S.out_pid[idx] = A.out_pid[k];
+            if (S.out_tid) S.out_tid[idx] = tid;
+        }
+        if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
+    }
+}
+
+// One Goto transition out of state s on byte b; returns next | final bit, or 0.
+__device__ __forceinline__ int32_t step_global(const DevAut &A, const uint8_t *cls, int32_t s, uint32_t b) {
+    if (s < A.S_dense) return A.dense[static_cast<int64_t>(s) * A.C + cls[b]];
+    const int32_t r = s - A.S_dense;
+    const int32_t fc = A.node[2 * r];
+    int32_t lo = 0, hi = A.node[2 * r + 1] & 0x7fffffff;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (A.label[fc + mid] < b) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < (A.node[2 * r + 1] & 0x7fffffff) && A.label[fc + lo] == b) {
+        const int32_t t = fc + lo;
+        return t | (A.node[2 * (t - A.S_dense) + 1] & kFinalBit);
+    }
+    return 0;
+}
+
+// Walks from offset o (relative to the start of the scanned buffer) and emits.
+__device__ void walk_from(const DevAut &A, const ScanArgs &S, const uint8_t *cls, int64_t o) {
+    int64_t end = S.n, tstart = 0;
+    int32_t tid = 0;
+    if (S.text_off) {
+        // largest t with text_off[t] - text_off[0] <= o
+        const int64_t base0 = S.text_off[0];
+        int32_t lo = 0, hi = S.n_texts;   // invariant: answer in [lo, hi)
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (S.text_off[mid] - base0 <= o) lo = mid;
+            else hi = mid;
+        }
+        tid = lo;
+        tstart = S.text_off[lo] - base0;
+        end = min(S.text_off[lo + 1] - base0, S.n);
+    }
+    int32_t s = 0;
+    for (int64_t j = o; j < end; ++j) {
+        const int32_t e = step_global(A, cls, s, S.text[j]);
+        if (e == 0) break;
+        s = e & 0x7fffffff;
+        if (e < 0) emit(A, S, o - tstart, tid, s);
+    }
+}
+
+struct FilterLaunch {
+    const uint8_t *base;     // text pointer rounded down to 16 bytes
+    int64_t mis;             // text - base
+    int64_t V;               // mis + n: end of the text in `base` coordinates
+    int64_t n_chunks;        // ceil(V / chunk bytes)
+    int64_t c_lo, c_hi;      // interior chunks [c_lo, c_hi): whole chunk + 16 B inside the text
+    int32_t filter_kind;
+};
+
+template <int SEGS>
+struct ChunkRegs {
+    uint32_t d[SEGS][4];
+    uint32_t tail;   // first dword after the chunk (halo of the last lane)
+};
+
+// Interior chunk: one coalesced 16-byte load per lane and segment.
+template <int SEGS>
+__device__ __forceinline__ void load_interior(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
+    constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
+    const uint8_t *p = F.base + c * CH + lane * 16;
+#pragma unroll
+    for (int j = 0; j < SEGS; ++j) {
+        const u32x4 q = gload16(p + j * kSegBytes);
+        R.d[j][0] = q.x; R.d[j][1] = q.y; R.d[j][2] = q.z; R.d[j][3] = q.w;
+    }
+    R.tail = gload4(F.base + (c + 1) * CH);
+}
+
+// Chunk that overlaps either end of the text: bytes outside it read as 0.
+template <int SEGS>
+__device__ __noinline__ void load_partial(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
+    constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
+    auto get4 = [&](int64_t p) {
+        uint32_t v = 0;
+        for (int b = 0; b < 4; ++b)
+            if (p + b >= F.mis && p + b < F.V) v |= uint32_t(F.base[p + b]) << (8 * b);
+        return v;
+    };
+#pragma unroll
+    for (int j = 0; j < SEGS; ++j)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) R.d[j][w] = get4(c * CH + j * kSegBytes + lane * 16 + w * 4);
+    R.tail = get4((c + 1) * CH);
+}
+
+// Candidate mask of one chunk: bit 16 j + s is set when the K bytes at offset
+// s of the lane's 16 bytes in segment j hash to a set filter entry.
+template <int K, bool BITMAP, int SEGS, int FLOG2>
+__device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
+                                                           const uint8_t *sfilt, uint32_t mul) {
+    constexpr uint32_t kmask = K >= 3 ? 0xFFFFFFu : ((1u << (8 * K)) - 1u);
+    // byte map: 2^FLOG2 entries; bit map: 2^(FLOG2-2) words of 32 bits
+    constexpr int shift = BITMAP ? 32 - (FLOG2 - 2) : 32 - FLOG2;
+    unsigned long long m = 0;
+#pragma unroll
+    for (int j = 0; j < SEGS; ++j) {
+        uint32_t d[5];
+        d[0] = R.d[j][0]; d[1] = R.d[j][1]; d[2] = R.d[j][2]; d[3] = R.d[j][3];
+        const uint32_t from_next_lane = __builtin_amdgcn_ds_bpermute(int((lane + 1) * 4), int(d[0]));
+        const uint32_t from_next_seg = (j + 1 < SEGS) ? __builtin_amdgcn_readlane(R.d[(j + 1) % SEGS][0], 0)
+                                                      : R.tail;
+        d[4] = lane == 63 ? from_next_seg : from_next_lane;
+        uint32_t mj = 0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int w = s >> 2, r = s & 3;
+            uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
+            if (K < 3) x &= kmask;
+            const uint32_t p = __umul24(x, mul);
+            uint32_t v;
+            if (BITMAP) v = __builtin_amdgcn_ubfe(reinterpret_cast<const uint32_t *>(sfilt)[p >> shift], p, 1u);
+            else v = sfilt[p >> shift];
+            mj |= v << s;
+        }
+        m |= static_cast<unsigned long long>(mj) << (16 * j);
+    }
+    return m;
+}
+
+template <int K, bool BITMAP, int SEGS, int FLOG2>
+__global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
+    __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
+    __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
+    __shared__ __align__(16) uint8_t scls[256];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[F.filter_kind - 1]);
+        uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
+        for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
+        if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
+            reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
+    }
+    __syncthreads();
+
+    constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
+    const unsigned lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const int waves_per_block = int(blockDim.x) / kWave;
+    uint32_t *q = squeue + wave * kQueueCap;
+    const int64_t w = int64_t(blockIdx.x) * waves_per_block + wave;
+    const int64_t nw = int64_t(gridDim.x) * waves_per_block;
+    const uint32_t mul = A.hash_mul;
+
+    // Queue entry = (k << 12) | position in chunk, for chunk qbase + k * qstride.
+    int64_t qbase = F.c_lo + w, qstride = nw;
+    int qlen = 0;
+    auto drain = [&](int take) {
+        // lanes [0, take) walk the newest `take` entries
+        wave_sync();
+        const uint32_t e = lane < unsigned(take) ? q[qlen - take + int(lane)] : 0u;
+        wave_sync();
+        qlen -= take;
+        if (lane < unsigned(take)) {
+            const int64_t o = (qbase + int64_t(e >> 12) * qstride) * CH + int64_t(e & 4095u) - F.mis;
+            walk_from(A, S, scls, o);
+        }
+    };
+    auto push = [&](unsigned long long m, uint32_t k) {
+        while (true) {
+            const unsigned long long act = __ballot(m != 0);
+            if (act == 0) break;
+            if (m) {
+                const int b = __ffsll(static_cast<long long>(m)) - 1;
+                q[qlen + int(rank_in(act))] = (k << 12) | uint32_t((b >> 4) * kSegBytes + int(lane) * 16 + (b & 15));
+                m &= m - 1;
+            }
+            qlen += __popcll(act);
+            while (qlen >= kWave) drain(kWave);
+        }
+    };
+
+    // interior chunks, two register sets in turn so that the next chunk's
+    // loads are in flight while this one is filtered
+    {
+        ChunkRegs<SEGS> ra, rb;
+        int64_t c = F.c_lo + w;
+        uint32_t k = 0;
+        if (c < F.c_hi) load_interior<SEGS>(F, c, lane, ra);
+        while (c < F.c_hi) {
+            const int64_t c1 = c + nw;
+            if (c1 < F.c_hi) load_interior<SEGS>(F, c1, lane, rb);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2>(ra, lane, sfilt, mul), k++);
+            c = c1;
+            if (c >= F.c_hi) break;
+            const int64_t c2 = c + nw;
+            if (c2 < F.c_hi) load_interior<SEGS>(F, c2, lane, ra);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2>(rb, lane, sfilt, mul), k++);
+            c = c2;
+        }
+        if (qlen > 0) drain(qlen);
+    }
+
+    // chunks overlapping an end of the text: [0, p0) and [p1, n_chunks)
+    const int64_t p0 = min(F.c_lo, F.n_chunks);
+    const int64_t p1 = max(F.c_hi, F.c_lo);
+    const int64_t n_partial = p0 + (F.n_chunks - p1);
+    for (int64_t i = w; i < n_partial; i += nw) {
+        const int64_t pc = i < p0 ? i : p1 + (i - p0);
+        ChunkRegs<SEGS> r;
+        load_partial<SEGS>(F, pc, lane, r);
+        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2>(r, lane, sfilt, mul);
+        for (int b = 0; b < SEGS * 16; ++b) {
+            // keep offsets o with 0 <= o and o + K <= n
+            const int64_t o = pc * CH + (b >> 4) * kSegBytes + int64_t(lane) * 16 + (b & 15) - F.mis;
+            if (o < 0 || o + K > S.n) m &= ~(1ull << b);
+        }
+        qbase = pc;
+        qstride = 0;
+        push(m, 0);
+        if (qlen > 0) drain(qlen);
+    }
+}
+
+// ---------------------------------------------------------------------------
+struct DirectLaunch {
+    int64_t tile;          // offsets per block
+    int32_t table_bytes;   // dense table bytes staged in LDS (0 = global)
+    int32_t halo;          // longest keyword - 1
+};
+
+template <bool TABLE_LDS>
+__global__ __launch_bounds__(1024) void direct_kernel(const DevAut A, const ScanArgs S, const DirectLaunch L) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t *scls = smem;
+    int32_t *stab = reinterpret_cast<int32_t *>(smem + 256);
+    uint8_t *stext = smem + 256 + (TABLE_LDS ? L.table_bytes : 0);
+    if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
+        reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
+    if (TABLE_LDS) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.dense);
+        uint4 *dst = reinterpret_cast<uint4 *>(stab);
+        for (int i = threadIdx.x; i < L.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
+    }
+    const int64_t t0 = int64_t(blockIdx.x) * L.tile;
+    const int64_t t1 = min(t0 + L.tile, S.n);
+    const int64_t h1 = min(t1 + L.halo, S.n);
+    for (int64_t i = threadIdx.x; i < h1 - t0; i += blockDim.x) stext[i] = S.text[t0 + i];
+    __syncthreads();
+    for (int64_t o = t0 + threadIdx.x; o < t1; o += blockDim.x) {
+        int32_t s = 0;
+        for (int64_t j = o; j < h1; ++j) {
+            const uint32_t b = stext[j - t0];
+            int32_t e;
+            if (TABLE_LDS) e = stab[s * A.C + scls[b]];
+            else e = step_global(A, scls, s, b);
+            if (e == 0) break;
+            s = e & 0x7fffffff;
+            if (e < 0) emit(A, S, o, 0, s);
+        }
+    }
+}
+
+__global__ void zero_kernel(unsigned long long *count, int64_t *per_text, int32_t n_texts) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) *count = 0ull;
+    if (per_text && i < n_texts) per_text[i] = 0;
+}
+
+using FilteredFn = void (*)(const DevAut, const ScanArgs, const FilterLaunch);
+
+template <int K, bool BM, int FLOG2>
+FilteredFn pick_segs(int segs) {
+    switch (segs) {
+        case 1: return filtered_kernel<K, BM, 1, FLOG2>;
+        case 2: return filtered_kernel<K, BM, 2, FLOG2>;
+        default: return filtered_kernel<K, BM, 4, FLOG2>;
+    }
+}
+
+template <int K>
+FilteredFn pick_filter(int kind, int segs) {
+    switch (kind) {
+        case AC_FILTER_BYTES17: return pick_segs<K, false, 17>(segs);
+        case AC_FILTER_BITS20: return pick_segs<K, true, 17>(segs);
+        case AC_FILTER_BYTES16: return pick_segs<K, false, 16>(segs);
+        default: return pick_segs<K, true, 16>(segs);
+    }
+}
+
+FilteredFn pick_filtered(int K, int kind, int segs) {
+    if (K == 1) return pick_filter<1>(kind, segs);
+    if (K == 2) return pick_filter<2>(kind, segs);
+    return pick_filter<3>(kind, segs);
+}
+
+int64_t filtered_lds(const FilterGeom &g) {
+    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + 256;
+}
+
+std::mutex g_attr_mu;
+
+void allow_lds(const void *fn, int64_t bytes) {
+    // Raise the dynamic-LDS limit of a kernel once (160 KiB per CU on gfx950).
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+}  // namespace
+
+void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg) {
+    const Plan &P = a->host;
+    if (cfg.policy == AC_POLICY_AUTO) cfg.policy = AC_POLICY_FILTERED;
+    if (batch) cfg.policy = AC_POLICY_FILTERED;
+    if (cfg.policy == AC_POLICY_FILTERED) {
+        if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_BITS19) {
+            const bool small_text = len < (int64_t(16) << 20);
+            const bool many = P.n_prefixes > 1500;
+            if (small_text) cfg.filter = many ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;
+            else cfg.filter = many ? AC_FILTER_BITS20 : AC_FILTER_BYTES17;
+        }
+        FilterGeom g = filter_geom(cfg.filter);
+        if (filtered_lds(g) > a->lds_per_block) {
+            // the 128 KiB maps need a 160 KiB LDS; fall back to the 64 KiB ones
+            if (cfg.filter == AC_FILTER_BYTES17) cfg.filter = AC_FILTER_BYTES16;
+            if (cfg.filter == AC_FILTER_BITS20) cfg.filter = AC_FILTER_BITS19;
+            g = filter_geom(cfg.filter);
+        }
+        if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = 4;
+        const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
+        if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
+    } else {
+        if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 256;
+        const int64_t table_bytes = int64_t(P.S_dense) * P.C * 4;
+        const bool fits = P.S_dense == P.S && table_bytes + 256 + 8192 + P.max_len + 64 <= a->lds_per_block;
+        if (cfg.table_in_lds == 1 && !fits) cfg.table_in_lds = 2;
+        if (cfg.table_in_lds != 1 && cfg.table_in_lds != 2) cfg.table_in_lds = fits ? 1 : 2;
+    }
+}
+
+int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts, hipStream_t stream,
+                std::string &err) {
+    const int32_t threads = 256;
+    const int32_t blocks = std::max<int32_t>(1, (std::max<int32_t>(n_texts, 1) + threads - 1) / threads);
+    zero_kernel<<<blocks, threads, 0, stream>>>(count, per_text, n_texts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { err = std::string("zero_kernel launch: ") + hipGetErrorString(e); return AC_EHIP; }
+    return AC_OK;
+}
+
+int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, hipStream_t stream,
+                std::string &err) {
+    if (S.n <= 0) return AC_OK;
+    const Plan &P = a->host;
+    hipError_t e = hipSuccess;
+    if (cfg.policy == AC_POLICY_FILTERED) {
+        const FilterGeom g = filter_geom(cfg.filter);
+        FilterLaunch F;
+        const uintptr_t addr = reinterpret_cast<uintptr_t>(S.text);
+        F.base = reinterpret_cast<const uint8_t *>(addr & ~uintptr_t(15));
+        F.mis = int64_t(addr & 15);
+        F.V = F.mis + S.n;
+        const int64_t CH = int64_t(cfg.segs) * kSegBytes;
+        F.n_chunks = (F.V + CH - 1) / CH;
+        F.c_lo = F.mis > 0 ? 1 : 0;
+        F.c_hi = F.V >= 16 ? (F.V - 16) / CH : 0;
+        F.filter_kind = g.kind;
+        const int waves = cfg.block / kWave;
+        const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
+        const int64_t want = (std::max<int64_t>(interior, 1) + waves - 1) / waves;
+        const int64_t cap = int64_t(a->cu_count) * cfg.grid_per_cu;
+        const int64_t grid = std::max<int64_t>(1, std::min(want, cap));
+        // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
+        if (interior / (grid * waves) >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
+        FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs);
+        hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
+        e = hipGetLastError();
+    } else if (cfg.policy == AC_POLICY_DIRECT) {
+        if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }
+        DirectLaunch L;
+        L.tile = 8192;
+        L.halo = P.max_len - 1;
+        const bool lds_table = cfg.table_in_lds == 1;
+        L.table_bytes = lds_table ? int32_t((int64_t(P.S_dense) * P.C * 4 + 15) / 16 * 16) : 0;
+        const int64_t lds = 256 + L.table_bytes + L.tile + L.halo + 16;
+        const int64_t grid = (S.n + L.tile - 1) / L.tile;
+        if (lds > a->lds_per_block) { err = "direct policy: tile and table exceed LDS"; return AC_ENOTSUP; }
+        auto fn = lds_table ? direct_kernel<true> : direct_kernel<false>;
+        allow_lds(reinterpret_cast<const void *>(fn), lds);
+        hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(unsigned(cfg.block)), size_t(lds), stream, a->dev, S, L);
+        e = hipGetLastError();
+    } else {
+        err = "unknown policy";
+        return AC_EINVAL;
+    }
+    if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
+    return AC_OK;
+}
+
+}  // namespace pfac

@@ -1,0 +1,117 @@
+// Internal structures shared by the host builder, the launch code and the
+// HIP kernels of the failure-less Aho-Corasick matcher.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pfac.h"
+
+namespace pfac {
+
+constexpr int kWave = 64;
+constexpr int kSegBytes = 1024;          // bytes one wave loads per segment (64 lanes x 16 B)
+constexpr int kMaxPrefix = 3;            // bytes hashed by the candidate filter
+constexpr uint32_t kDefaultHashMul = 0x9E3779u;   // odd 24-bit multiplier
+constexpr int64_t kDefaultDenseBudget = 64ll << 20;
+constexpr int32_t kFinalBit = int32_t(0x80000000u);
+
+// Filter geometry: index bits taken from the top of the 32-bit product.
+struct FilterGeom {
+    int kind;        // AC_FILTER_*
+    bool bitmap;     // false: one byte per entry; true: one bit per entry
+    int index_bits;  // log2(entries)
+    int shift;       // product >> shift gives the byte (byte map) or word (bit map) index
+    int64_t bytes;   // LDS bytes
+};
+
+inline FilterGeom filter_geom(int kind) {
+    switch (kind) {
+        case AC_FILTER_BYTES17: return {kind, false, 17, 32 - 17, 1ll << 17};
+        case AC_FILTER_BITS20:  return {kind, true, 20, 32 - 15, 1ll << 17};
+        case AC_FILTER_BYTES16: return {kind, false, 16, 32 - 16, 1ll << 16};
+        case AC_FILTER_BITS19:  return {kind, true, 19, 32 - 14, 1ll << 16};
+        default: return {0, false, 0, 0, 0};
+    }
+}
+constexpr int kNumFilters = 4;
+
+// Host-side build result (the "plan").  States are numbered breadth first,
+// so the children of a state are contiguous and sorted by byte, and every
+// state of depth <= dense_depth precedes every deeper state.
+struct Plan {
+    int32_t n_patterns = 0;
+    std::vector<int64_t> kw_len;
+    int32_t S = 0;                 // states, root = 0
+    int32_t C = 0;                 // classes
+    uint8_t cls[256] = {};
+    int32_t min_len = 0, max_len = 0, K = 0;
+    std::vector<int32_t> depth, first_child, n_child;
+    std::vector<uint8_t> label;
+    std::vector<int32_t> out_off, out_pid;
+    int32_t S_dense = 0, dense_depth = 0;
+    std::vector<int32_t> dense;    // [S_dense * C]
+    std::vector<int32_t> node;     // [2 * (S - S_dense)]
+    uint32_t hash_mul = kDefaultHashMul;
+    int32_t n_prefixes = 0;
+    std::vector<uint8_t> filter[kNumFilters];   // indexed by kind - 1
+    double build_ms = 0.0;
+};
+
+// Kernel-side view of a device automaton (passed by value).
+struct DevAut {
+    const uint8_t *cls;
+    const uint8_t *filter[kNumFilters];
+    const int32_t *dense;
+    const int32_t *node;
+    const uint8_t *label;
+    const int32_t *out_off;
+    const int32_t *out_pid;
+    int32_t C, S, S_dense, K, max_len;
+    uint32_t hash_mul;
+};
+
+// Arguments of one scan launch.
+struct ScanArgs {
+    const uint8_t *text;           // first byte of the (packed) text
+    int64_t n;                     // bytes
+    const int64_t *text_off;       // batch: device int64[n_texts + 1]; nullptr = single text
+    int32_t n_texts;
+    int64_t *out_off;              // match offsets (relative to its text)
+    int32_t *out_pid;
+    int32_t *out_tid;              // batch only
+    int64_t cap;                   // 0 = count only
+    unsigned long long *count;
+    int64_t *per_text;             // batch only, may be null
+};
+
+}  // namespace pfac
+
+struct ac_plan {
+    pfac::Plan p;
+};
+
+struct ac_automaton {
+    pfac::Plan host;               // tables kept for ac_info and launch decisions
+    int device = 0;
+    void *dmem = nullptr;          // one device allocation for every table
+    int64_t dbytes = 0;
+    pfac::DevAut dev{};
+    int cu_count = 0;
+    int64_t lds_per_block = 0;
+    int64_t lds_per_cu = 0;
+};
+
+namespace pfac {
+// plan.cpp
+int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
+                 const ac_build_opts *opts, Plan &out, std::string &err);
+uint32_t prefix_hash(uint32_t x, uint32_t mul);
+// kernels.hip
+int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg,
+                hipStream_t stream, std::string &err);
+int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
+                hipStream_t stream, std::string &err);
+void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg);
+}  // namespace pfac

@@ -1,0 +1,228 @@
+// Host-side automaton builder for the failure-less Aho-Corasick matcher.
+//
+// Builds the Goto trie of the keyword set (paper, Section II and Fig. 5: the
+// failure-less machine is the Goto function alone plus the Output lists),
+// numbers its states breadth first, compresses the byte alphabet into classes
+// and lays the transitions out for the GPU:
+//
+//   * dense rows  int32[C] for every state of depth <= D, where D is the
+//     largest depth whose rows fit the dense budget.  Entry = next state with
+//     bit 31 set when that state ends a keyword; 0 = no transition (the root
+//     is never a target, so 0 is free to mean "dead");
+//   * compact nodes for deeper states: (first child, child count | final bit)
+//     with the children's edge bytes in `label`, contiguous and sorted by the
+//     breadth-first numbering;
+//   * Output lists as CSR (keyword ids ending at each state, ascending);
+//   * candidate filters: each keyword's first K = min(3, shortest keyword)
+//     bytes hashed into byte maps and bit maps sized for LDS.
+//
+// The trie is built from the keywords in lexicographic order, which creates
+// each state's children in increasing byte order without any hashing.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+
+#include "pfac_internal.hpp"
+
+namespace pfac {
+
+uint32_t prefix_hash(uint32_t x, uint32_t mul) {
+    // Same arithmetic as the kernel's 24 x 24-bit multiply (low 32 bits).
+    return uint32_t(uint64_t(x & 0xFFFFFFu) * uint64_t(mul & 0xFFFFFFu));
+}
+
+int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
+                 const ac_build_opts *opts, Plan &P, std::string &err) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (n <= 0) { err = "ac_build: need at least one keyword"; return AC_EINVAL; }
+    if (!bytes || !offsets) { err = "ac_build: NULL keyword buffer"; return AC_EINVAL; }
+    int64_t dense_budget = (opts && opts->dense_budget_bytes > 0) ? opts->dense_budget_bytes
+                                                                   : kDefaultDenseBudget;
+    uint32_t mul = (opts && opts->hash_multiplier) ? (opts->hash_multiplier & 0xFFFFFFu) | 1u
+                                                   : kDefaultHashMul;
+    P = Plan();
+    P.n_patterns = n;
+    P.hash_mul = mul;
+    P.kw_len.resize(n);
+    int64_t total = 0;
+    P.min_len = INT32_MAX;
+    for (int32_t p = 0; p < n; ++p) {
+        int64_t L = offsets[p + 1] - offsets[p];
+        if (L <= 0) { err = "ac_build: keyword " + std::to_string(p) + " is empty"; return AC_EINVAL; }
+        if (L > (1 << 30)) { err = "ac_build: keyword longer than 2^30 bytes"; return AC_EINVAL; }
+        P.kw_len[p] = L;
+        total += L;
+        P.min_len = std::min<int64_t>(P.min_len, L);
+        P.max_len = std::max<int64_t>(P.max_len, L);
+    }
+    if (total >= (int64_t(1) << 31) - 1) { err = "ac_build: more than 2^31 trie states"; return AC_EINVAL; }
+    P.K = std::min(kMaxPrefix, P.min_len);
+
+    // ---- Goto trie, built in lexicographic keyword order -------------------
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto kw = [&](int32_t p) { return bytes + offsets[p]; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        int64_t la = P.kw_len[a], lb = P.kw_len[b];
+        int c = std::memcmp(kw(a), kw(b), size_t(std::min(la, lb)));
+        if (c) return c < 0;
+        return la < lb;
+    });
+    // creation-order trie: parent, edge byte, depth; terminal state per keyword
+    std::vector<int32_t> parent(1, -1), cdepth(1, 0);
+    std::vector<uint8_t> clabel(1, 0);
+    std::vector<int32_t> terminal(n, 0);
+    std::vector<int32_t> path(1, 0);
+    parent.reserve(size_t(total) + 1);
+    cdepth.reserve(size_t(total) + 1);
+    clabel.reserve(size_t(total) + 1);
+    int32_t prev = -1;
+    for (int32_t idx = 0; idx < n; ++idx) {
+        int32_t p = order[idx];
+        int64_t L = P.kw_len[p], lcp = 0;
+        if (prev >= 0) {
+            int64_t m = std::min(L, P.kw_len[prev]);
+            const uint8_t *a = kw(p), *b = kw(prev);
+            while (lcp < m && a[lcp] == b[lcp]) ++lcp;
+        }
+        path.resize(size_t(lcp) + 1);
+        for (int64_t d = lcp; d < L; ++d) {
+            int32_t t = int32_t(parent.size());
+            parent.push_back(path[size_t(d)]);
+            clabel.push_back(kw(p)[d]);
+            cdepth.push_back(int32_t(d + 1));
+            path.push_back(t);
+        }
+        terminal[p] = path[size_t(L)];
+        prev = p;
+    }
+    const int32_t S = int32_t(parent.size());
+    P.S = S;
+
+    // children lists in creation order (already sorted by byte)
+    std::vector<int32_t> ch_off(size_t(S) + 1, 0), ch(size_t(S > 0 ? S - 1 : 0));
+    for (int32_t t = 1; t < S; ++t) ch_off[size_t(parent[t]) + 1]++;
+    for (int32_t s = 0; s < S; ++s) ch_off[size_t(s) + 1] += ch_off[size_t(s)];
+    {
+        std::vector<int32_t> fill(ch_off.begin(), ch_off.end() - 1);
+        for (int32_t t = 1; t < S; ++t) ch[size_t(fill[size_t(parent[t])]++)] = t;
+    }
+
+    // ---- breadth-first numbering ------------------------------------------
+    std::vector<int32_t> bfs(static_cast<size_t>(S)), newid(static_cast<size_t>(S));
+    bfs[0] = 0;
+    newid[0] = 0;
+    int64_t head = 0, tail = 1;
+    while (head < tail) {
+        int32_t s = bfs[size_t(head++)];
+        for (int32_t e = ch_off[size_t(s)]; e < ch_off[size_t(s) + 1]; ++e) {
+            int32_t t = ch[size_t(e)];
+            newid[size_t(t)] = int32_t(tail);
+            bfs[size_t(tail++)] = t;
+        }
+    }
+    P.depth.resize(size_t(S));
+    P.first_child.assign(size_t(S), 0);
+    P.n_child.assign(size_t(S), 0);
+    P.label.assign(size_t(S), 0);
+    for (int32_t i = 0; i < S; ++i) {
+        int32_t s = bfs[size_t(i)];
+        P.depth[size_t(i)] = cdepth[size_t(s)];
+        P.label[size_t(i)] = clabel[size_t(s)];
+        int32_t nc = ch_off[size_t(s) + 1] - ch_off[size_t(s)];
+        P.n_child[size_t(i)] = nc;
+        P.first_child[size_t(i)] = nc ? newid[size_t(ch[size_t(ch_off[size_t(s)])])] : 0;
+    }
+
+    // ---- Output lists: keyword ids per state, ascending -------------------
+    P.out_off.assign(size_t(S) + 1, 0);
+    for (int32_t p = 0; p < n; ++p) P.out_off[size_t(newid[size_t(terminal[p])]) + 1]++;
+    for (int32_t s = 0; s < S; ++s) P.out_off[size_t(s) + 1] += P.out_off[size_t(s)];
+    P.out_pid.resize(size_t(n));
+    {
+        std::vector<int32_t> fill(P.out_off.begin(), P.out_off.end() - 1);
+        for (int32_t p = 0; p < n; ++p) P.out_pid[size_t(fill[size_t(newid[size_t(terminal[p])])]++)] = p;
+    }
+    auto is_final = [&](int32_t s) { return P.out_off[size_t(s) + 1] > P.out_off[size_t(s)]; };
+
+    // ---- alphabet compression ---------------------------------------------
+    bool used[256] = {};
+    for (int32_t p = 0; p < n; ++p)
+        for (int64_t j = 0; j < P.kw_len[p]; ++j) used[kw(p)[j]] = true;
+    int n_used = 0;
+    for (int b = 0; b < 256; ++b) n_used += used[b];
+    if (n_used == 256) {
+        P.C = 256;
+        for (int b = 0; b < 256; ++b) P.cls[b] = uint8_t(b);
+    } else {
+        P.C = n_used + 1;                       // class 0 = bytes in no keyword
+        int c = 1;
+        for (int b = 0; b < 256; ++b) P.cls[b] = used[b] ? uint8_t(c++) : 0;
+    }
+
+    // ---- dense rows for the shallow states, compact nodes below ------------
+    const int64_t row_bytes = int64_t(P.C) * 4;
+    int32_t D = 0, S_dense = 1;
+    {
+        // states are depth-sorted: count states per depth
+        int32_t maxd = P.depth[size_t(S - 1)];
+        std::vector<int64_t> upto(size_t(maxd) + 1, 0);
+        for (int32_t i = 0; i < S; ++i) upto[size_t(P.depth[size_t(i)])]++;
+        int64_t acc = 0;
+        for (int32_t d = 0; d <= maxd; ++d) {
+            acc += upto[size_t(d)];
+            if (d == 0 || acc * row_bytes <= dense_budget) {
+                D = d;
+                S_dense = int32_t(acc);
+            } else {
+                break;
+            }
+        }
+    }
+    P.dense_depth = D;
+    P.S_dense = S_dense;
+    P.dense.assign(size_t(S_dense) * size_t(P.C), 0);
+    for (int32_t s = 0; s < S_dense; ++s) {
+        for (int32_t k = 0; k < P.n_child[size_t(s)]; ++k) {
+            int32_t t = P.first_child[size_t(s)] + k;
+            int32_t e = t | (is_final(t) ? kFinalBit : 0);
+            P.dense[size_t(s) * size_t(P.C) + P.cls[P.label[size_t(t)]]] = e;
+        }
+    }
+    P.node.assign(size_t(S - S_dense) * 2, 0);
+    for (int32_t s = S_dense; s < S; ++s) {
+        size_t i = size_t(s - S_dense) * 2;
+        P.node[i] = P.first_child[size_t(s)];
+        P.node[i + 1] = P.n_child[size_t(s)] | (is_final(s) ? kFinalBit : 0);
+    }
+
+    // ---- candidate filters over the first K bytes of every keyword --------
+    std::vector<uint32_t> prefixes(static_cast<size_t>(n));
+    for (int32_t p = 0; p < n; ++p) {
+        uint32_t x = 0;
+        for (int j = 0; j < P.K; ++j) x |= uint32_t(kw(p)[j]) << (8 * j);
+        prefixes[size_t(p)] = x;
+    }
+    std::sort(prefixes.begin(), prefixes.end());
+    prefixes.erase(std::unique(prefixes.begin(), prefixes.end()), prefixes.end());
+    P.n_prefixes = int32_t(prefixes.size());
+    for (int kind = 1; kind <= kNumFilters; ++kind) {
+        FilterGeom g = filter_geom(kind);
+        std::vector<uint8_t> &f = P.filter[kind - 1];
+        f.assign(size_t(g.bytes), 0);
+        for (uint32_t x : prefixes) {
+            uint32_t h = prefix_hash(x, mul);
+            if (g.bitmap) {
+                uint32_t w = h >> g.shift, bit = h & 31u;
+                f[size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
+            } else {
+                f[size_t(h >> g.shift)] = 1;
+            }
+        }
+    }
+    P.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return AC_OK;
+}
+
+}  // namespace pfac

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP matcher against the CPU oracle, bit-exact.
+
+Every case compares the sorted (offset, keyword id) set of the GPU with the
+serial Aho-Corasick oracle on the same seeded input.  Kernels are reached only
+through the C ABI (via the ctypes binding).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle_match
+from tests.helpers import assert_same
+from workloads import config_tiny
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+pf = None
+
+
+def setup_module(module):
+    global pf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1412_7789_amd as _pf
+    _pf.load()          # fails loudly when the HIP library is missing
+    pf = _pf
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_match(keywords, text, launch=None, offset=0, automaton=None):
+    """Run through the C ABI; `offset` shifts the text inside its buffer to test alignment."""
+    a = automaton or pf.Automaton(keywords)
+    buf = np.zeros(len(text) + offset + 16, dtype=np.uint8)
+    buf[offset:offset + len(text)] = np.frombuffer(bytes(text), dtype=np.uint8) if not isinstance(text, np.ndarray) else text
+    d = torch.from_numpy(buf).cuda()
+    t = d[offset:offset + len(text)]
+    off, pid = a.match(t, launch=launch)
+    return off.cpu().numpy(), pid.cpu().numpy()
+
+
+POLICIES = [
+    ("filtered-bytes17-s4", dict(policy=1, filter=1, segs=4)),
+    ("filtered-bits20-s2", dict(policy=1, filter=2, segs=2)),
+    ("filtered-bytes16-s1", dict(policy=1, filter=3, segs=1)),
+    ("filtered-bits19-s4-b256", dict(policy=1, filter=4, segs=4, block=256)),
+    ("filtered-bytes17-s2-b512", dict(policy=1, filter=1, segs=2, block=512)),
+    ("direct-lds", dict(policy=2, table_in_lds=1)),
+    ("direct-global", dict(policy=2, table_in_lds=2)),
+]
+
+
+def test_fig4_keywords():
+    kws = [b"AB", b"ABG", b"BEDE", b"ED"]
+    for text in [b"ABGBEDED", b"ABGBEDED" * 1000, b"xBEDEDABG" * 777]:
+        say("fig4", len(text))
+        assert_same(gpu_match(kws, text), oracle_match(kws, text), "fig4")
+
+
+@pytest.mark.parametrize("name,cfg", POLICIES)
+def test_tiny_config_all_policies(name, cfg):
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    exp = oracle_match(w.keywords, w.text)
+    say("tiny", name)
+    got = gpu_match(w.keywords, w.text, launch=pf.launch_config(**cfg), automaton=a)
+    assert_same(got, exp, f"tiny {name}")
+
+
+@pytest.mark.parametrize("offset", [0, 1, 3, 7, 15])
+def test_unaligned_text_and_ragged_lengths(offset):
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    for n in [0, 1, 2, 3, 11, 15, 16, 17, 1023, 1024, 1025, 4095, 4096, 4097, 4111, 4112, 4113,
+              65535, 65536 + 7, 200_003]:
+        text = w.text[:n]
+        say("unaligned", offset, n)
+        assert_same(gpu_match(w.keywords, text, offset=offset, automaton=a),
+                    oracle_match(w.keywords, text), f"offset {offset} n {n}")
+
+
+def test_hand_built_edge_cases():
+    cases = [
+        ([b"abab"], b"ababab"),
+        ([b"a", b"ab", b"abc", b"bc", b"c"], b"abc" * 500),
+        ([b"ab", b"ab"], b"abab" * 300),                  # duplicate keywords
+        ([b"hello"], b"hello"),                           # keyword = text
+        ([b"hello!"], b"hello"),                          # keyword longer than text
+        ([b"x" * 64], b"x" * 5000),                       # long self-overlapping keyword
+        ([b"\x00", b"\xff", b"\x00\xff"], bytes([0, 255] * 3000)),
+        ([b"aa"], b"a" * 10_000),
+        ([b"q"], b""),
+    ]
+    for kws, text in cases:
+        say("edge", kws[:3], len(text))
+        assert_same(gpu_match(kws, text), oracle_match(kws, text), repr(kws[:3]))
+
+
+def test_every_single_byte_keyword():
+    rng = np.random.default_rng(11)
+    kws = [bytes([b]) for b in range(256)]
+    text = rng.integers(0, 256, size=50_000, dtype=np.uint8)
+    for name, cfg in POLICIES:
+        say("single-byte", name)
+        assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)),
+                    oracle_match(kws, text), f"single bytes {name}")
+
+
+def test_plants_straddling_chunk_boundaries():
+    """Keywords planted across every position near 1 KiB / 2 KiB / 4 KiB
+    boundaries, for each chunk geometry."""
+    rng = np.random.default_rng(5)
+    kws = [bytes(rng.integers(97, 123, size=L, dtype=np.uint8)) for L in (4, 7, 12, 31, 64)]
+    text = rng.integers(97, 123, size=3 * 4096 + 100, dtype=np.uint8)
+    texts = []
+    for boundary in (1024, 2048, 4096, 8192):
+        for k in kws:
+            for d in range(-len(k) - 1, 2):
+                t = text.copy()
+                o = boundary + d
+                if 0 <= o and o + len(k) <= len(t):
+                    t[o:o + len(k)] = np.frombuffer(k, dtype=np.uint8)
+                    texts.append(t)
+    a = pf.Automaton(kws)
+    for segs in (1, 2, 4):
+        cfg = pf.launch_config(policy=1, segs=segs)
+        for i, t in enumerate(texts):
+            if i % 16 == 0:
+                say("straddle", segs, i)
+            assert_same(gpu_match(kws, t, launch=cfg, automaton=a), oracle_match(kws, t), f"segs {segs} #{i}")
+
+
+def test_capacity_overflow_returns_true_count():
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    t = torch.from_numpy(w.text).cuda()
+    exp_off, exp_pid = oracle_match(w.keywords, w.text)
+    n = len(exp_off)
+    assert a.count(t) == n
+    for cap in (0, 1, n - 1, n):
+        off = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+        pid = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        got = a.match_into(t, off[:cap], pid[:cap])
+        assert got == n
+        exp = set(zip(exp_off.tolist(), exp_pid.tolist()))
+        sub = set(zip(off[:cap].cpu().tolist(), pid[:cap].cpu().tolist()))
+        assert len(sub) == cap and sub <= exp
+
+
+def test_errors_are_reported():
+    with pytest.raises(pf.PfacError):
+        pf.Automaton([b"ok", b""])
+    a = pf.Automaton([b"abc"])
+    t = torch.zeros(10, dtype=torch.uint8, device="cuda")
+    with pytest.raises(pf.PfacError):
+        a.count(t, launch=pf.launch_config(block=100))
