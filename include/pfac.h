@@ -102,8 +102,14 @@ typedef struct {
     int32_t segs;           /* 1 KiB segments per wave step: 1, 2 or 4; 0 = auto */
     int32_t grid_per_cu;    /* resident blocks per compute unit; 0 = auto        */
     int32_t table_in_lds;   /* DIRECT: -1/0 = auto, 1 = force LDS, 2 = global     */
-    int32_t reserved[6];
+    int32_t flags;          /* AC_LAUNCH_* bits                                   */
+    int32_t reserved[5];
 } ac_launch;
+
+/* Record HIP events on the call's stream immediately before and after the
+ * scan kernel; a synchronous call then leaves the kernel's duration for
+ * ac_last_scan_ms() in the calling thread. */
+#define AC_LAUNCH_TIME_SCAN 1
 
 /*
  * Match every occurrence in d_text[0 .. len) (device).  Writes up to
@@ -174,7 +180,9 @@ typedef struct {
     int32_t reserved0;
     int64_t dense_bytes, compact_bytes, output_bytes, filter_bytes, device_bytes;
     double build_ms;         /* host build + upload time                        */
-    int32_t reserved[8];
+    int64_t prefix_table_bytes;  /* exact prefix -> state table                 */
+    int64_t tail_bytes;      /* forced-path leaves + keyword bytes               */
+    int32_t reserved[4];
 } ac_info_t;
 
 int ac_info(const ac_automaton *a, ac_info_t *out);
@@ -183,6 +191,19 @@ int ac_info(const ac_automaton *a, ac_info_t *out);
 int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
 
 const char *ac_last_error(void);
+
+/* Scan-kernel milliseconds of this thread's last synchronous call made with
+ * AC_LAUNCH_TIME_SCAN (negative if none). */
+float ac_last_scan_ms(void);
+
+/* ---- measurement probe -------------------------------------------------------- */
+/*
+ * Reads d_buf[0 .. n) (device, 16-byte aligned, n a multiple of 16) once with
+ * coalesced 16-byte loads and folds it into *d_out (device uint32), so that
+ * the achievable HBM read bandwidth can be timed beside the scan.  Async on
+ * `stream`.  Errors: AC_EINVAL (misaligned or NULL), AC_EHIP.
+ */
+int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t stream);
 
 /* ---- host-side build, for inspection (no GPU needed) ------------------------ */
 /*
@@ -198,6 +219,8 @@ const char *ac_last_error(void);
  *   AC_TABLE_OUT_OFF    int32[S+1]         CSR offsets into AC_TABLE_OUT_PID
  *   AC_TABLE_OUT_PID    int32[...]         keyword ids ending at each state
  *   AC_TABLE_DEPTH      int32[S]           trie depth of each state
+ *   AC_TABLE_PREFIX     uint32[2*slots]    {prefix | 1<<31, state | final bit}, 0 = empty
+ *   AC_TABLE_TAIL       int32[S]           leaf reached by a forced path, or -1
  *   AC_TABLE_FILTER_*   filter maps (AC_FILTER_* + 100)
  */
 #define AC_TABLE_CLASS_MAP  1
@@ -207,6 +230,8 @@ const char *ac_last_error(void);
 #define AC_TABLE_OUT_OFF    5
 #define AC_TABLE_OUT_PID    6
 #define AC_TABLE_DEPTH      7
+#define AC_TABLE_PREFIX     8
+#define AC_TABLE_TAIL       9
 #define AC_TABLE_FILTER_BASE 100
 
 int ac_compile(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns,

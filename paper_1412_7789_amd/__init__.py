@@ -9,6 +9,6 @@ library was not built.
 from ._lib import (  # noqa: F401
     AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT,
     AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19,
-    EXPORTS, LIB_PATH, PfacError, load,
+    AC_LAUNCH_TIME_SCAN, EXPORTS, LIB_PATH, PfacError, load,
 )
-from .api import Automaton, Plan, launch_config, sorted_pairs  # noqa: F401
+from .api import Automaton, Plan, last_scan_ms, launch_config, probe_read, sorted_pairs  # noqa: F401

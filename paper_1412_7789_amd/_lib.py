@@ -13,14 +13,16 @@ AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
 AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19 = 0, 1, 2, 3, 4
 AC_TABLE_CLASS_MAP, AC_TABLE_DENSE, AC_TABLE_NODE, AC_TABLE_LABEL = 1, 2, 3, 4
 AC_TABLE_OUT_OFF, AC_TABLE_OUT_PID, AC_TABLE_DEPTH, AC_TABLE_FILTER_BASE = 5, 6, 7, 100
+AC_TABLE_PREFIX, AC_TABLE_TAIL = 8, 9
 
 # every symbol include/pfac.h declares
 EXPORTS = [
     "ac_build", "ac_build_csr", "ac_free", "ac_match", "ac_match_ex", "ac_match_async",
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
-    "ac_plan_free",
+    "ac_plan_free", "ac_last_scan_ms", "ac_probe_read",
 ]
+AC_LAUNCH_TIME_SCAN = 1
 
 
 class BuildOpts(ctypes.Structure):
@@ -40,7 +42,7 @@ class BatchMatches(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("filter", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("segs", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -54,7 +56,8 @@ class Info(ctypes.Structure):
                 ("dense_bytes", ctypes.c_int64), ("compact_bytes", ctypes.c_int64),
                 ("output_bytes", ctypes.c_int64), ("filter_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("prefix_table_bytes", ctypes.c_int64), ("tail_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -91,6 +94,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_plan_export": (i64, [vp, i32, vp, i64]),
         "ac_plan_hash": (u32, [vp, u32]),
         "ac_plan_free": (None, [vp]),
+        "ac_last_scan_ms": (ctypes.c_float, []),
+        "ac_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

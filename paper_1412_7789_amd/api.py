@@ -30,11 +30,24 @@ def _csr(keywords: Sequence[bytes]) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def launch_config(policy: int = 0, filter: int = 0, block: int = 0, segs: int = 0,
-                  grid_per_cu: int = 0, table_in_lds: int = 0) -> L.Launch:
+                  grid_per_cu: int = 0, table_in_lds: int = 0, flags: int = 0) -> L.Launch:
     cfg = L.Launch()
     cfg.policy, cfg.filter, cfg.block, cfg.segs = policy, filter, block, segs
-    cfg.grid_per_cu, cfg.table_in_lds = grid_per_cu, table_in_lds
+    cfg.grid_per_cu, cfg.table_in_lds, cfg.flags = grid_per_cu, table_in_lds, flags
     return cfg
+
+
+def last_scan_ms() -> float:
+    """Scan-kernel time of this thread's last synchronous call made with
+    ``flags=AC_LAUNCH_TIME_SCAN`` (HIP events on the call's stream)."""
+    return float(L.load().ac_last_scan_ms())
+
+
+def probe_read(buf, out, stream=None) -> None:
+    """Enqueue the read-bandwidth probe over a uint8 CUDA tensor (16-byte
+    aligned, length a multiple of 16); ``out`` is a 1-element int32 tensor."""
+    L.check(L.load().ac_probe_read(ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "ac_probe_read")
 
 
 def _opts(dense_budget_bytes: int, hash_multiplier: int) -> L.BuildOpts:

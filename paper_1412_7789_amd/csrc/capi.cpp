@@ -18,6 +18,7 @@ using namespace pfac;
 namespace {
 
 thread_local std::string g_err;
+thread_local float g_scan_ms = -1.0f;
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -33,6 +34,7 @@ int hip_fail(const char *what, hipError_t e) {
 struct CountSlot {
     unsigned long long *d = nullptr;
     unsigned long long *h = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // scan timing, created on first use
 };
 std::mutex g_slots_mu;
 std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
@@ -47,6 +49,8 @@ int count_slot(int device, hipStream_t stream, CountSlot &out) {
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
     e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocDefault);
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
+    if ((e = hipEventCreate(&s.ev0)) != hipSuccess || (e = hipEventCreate(&s.ev1)) != hipSuccess)
+        return hip_fail("hipEventCreate", e);
     g_slots[key] = s;
     out = s;
     return AC_OK;
@@ -87,6 +91,10 @@ int upload(ac_automaton *a) {
     Sec label{P.label.data(), int64_t(P.label.size()), 0};
     Sec ooff{P.out_off.data(), int64_t(P.out_off.size()) * 4, 0};
     Sec opid{P.out_pid.data(), int64_t(P.out_pid.size()) * 4, 0};
+    Sec ptab{P.ptab.data(), int64_t(P.ptab.size()) * 4, 0};
+    Sec tail{P.tail.data(), int64_t(P.tail.size()) * 4, 0};
+    Sec kwb{P.kw_bytes.data(), int64_t(P.kw_bytes.size()), 0};
+    Sec kwo{P.kw_off.data(), int64_t(P.kw_off.size()) * 4, 0};
     int64_t at = 0;
     auto place = [&](Sec &s) { s.at = at; at += pad256(std::max<int64_t>(s.bytes, 1)); };
     place(cls);
@@ -95,10 +103,12 @@ int upload(ac_automaton *a) {
         place(filt[k]);
     }
     place(dense); place(node); place(label); place(ooff); place(opid);
+    place(ptab); place(tail); place(kwb); place(kwo);
     a->dbytes = at;
     std::vector<uint8_t> staging(size_t(at), 0);
     auto copy = [&](const Sec &s) { if (s.bytes) std::memcpy(staging.data() + s.at, s.src, size_t(s.bytes)); };
     copy(cls); for (auto &f : filt) copy(f); copy(dense); copy(node); copy(label); copy(ooff); copy(opid);
+    copy(ptab); copy(tail); copy(kwb); copy(kwo);
     e = hipMalloc(&a->dmem, size_t(at));
     if (e != hipSuccess) { a->dmem = nullptr; return fail(AC_ENOMEM, std::string("hipMalloc(automaton): ") + hipGetErrorString(e)); }
     e = hipMemcpy(a->dmem, staging.data(), size_t(at), hipMemcpyHostToDevice);
@@ -112,6 +122,11 @@ int upload(ac_automaton *a) {
     D.label = b + label.at;
     D.out_off = reinterpret_cast<const int32_t *>(b + ooff.at);
     D.out_pid = reinterpret_cast<const int32_t *>(b + opid.at);
+    D.ptab = reinterpret_cast<const uint32_t *>(b + ptab.at);
+    D.tail = reinterpret_cast<const int32_t *>(b + tail.at);
+    D.kw_bytes = b + kwb.at;
+    D.kw_off = reinterpret_cast<const int32_t *>(b + kwo.at);
+    D.ptab_bits = P.ptab_bits;
     D.C = P.C;
     D.S = P.S;
     D.S_dense = P.S_dense;
@@ -135,8 +150,11 @@ void fill_info(const Plan &P, ac_info_t *o) {
     o->dense_bytes = int64_t(P.dense.size()) * 4;
     o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
     o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;
+    o->prefix_table_bytes = int64_t(P.ptab.size()) * 4;
+    o->tail_bytes = int64_t(P.tail.size()) * 4 + int64_t(P.kw_bytes.size()) + int64_t(P.kw_off.size()) * 4;
     for (const auto &f : P.filter) o->filter_bytes += int64_t(f.size());
-    o->device_bytes = 256 + o->dense_bytes + o->compact_bytes + o->output_bytes + o->filter_bytes;
+    o->device_bytes = 256 + o->dense_bytes + o->compact_bytes + o->output_bytes + o->filter_bytes +
+                      o->prefix_table_bytes + o->tail_bytes;
     o->build_ms = P.build_ms;
 }
 
@@ -149,6 +167,7 @@ int check_launch(const ac_launch *l) {
     if (l->segs != 0 && l->segs != 1 && l->segs != 2 && l->segs != 4)
         return fail(AC_EINVAL, "ac_launch: segs must be 1, 2 or 4");
     if (l->grid_per_cu < 0 || l->grid_per_cu > 64) return fail(AC_EINVAL, "ac_launch: bad grid_per_cu");
+    if (l->flags & ~AC_LAUNCH_TIME_SCAN) return fail(AC_EINVAL, "ac_launch: unknown flags");
     return AC_OK;
 }
 
@@ -162,7 +181,7 @@ int device_matches(const ac_automaton *a) {
 
 // Enqueue zero + scan for one text or a batch.
 int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch,
-            unsigned long long *d_count, hipStream_t stream) {
+            unsigned long long *d_count, hipStream_t stream, const CountSlot *timing = nullptr) {
     ac_launch cfg{};
     if (launch) cfg = *launch;
     if (batch && cfg.policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
@@ -171,8 +190,16 @@ int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool bat
     std::string err;
     int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
     if (rc) return fail(rc, err);
+    if (timing) {
+        hipError_t e = hipEventRecord(timing->ev0, stream);
+        if (e != hipSuccess) return hip_fail("hipEventRecord", e);
+    }
     rc = launch_scan(a, S, cfg, stream, err);
     if (rc) return fail(rc, err);
+    if (timing) {
+        hipError_t e = hipEventRecord(timing->ev1, stream);
+        if (e != hipSuccess) return hip_fail("hipEventRecord", e);
+    }
     return AC_OK;
 }
 
@@ -180,12 +207,19 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     CountSlot slot;
     int rc = count_slot(a->device, stream, slot);
     if (rc) return rc;
-    rc = enqueue(a, S, launch, batch, slot.d, stream);
+    const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN);
+    g_scan_ms = -1.0f;
+    rc = enqueue(a, S, launch, batch, slot.d, stream, timed ? &slot : nullptr);
     if (rc) return rc;
     hipError_t e = hipMemcpyAsync(slot.h, slot.d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    if (timed && S.n > 0) {
+        float ms = -1.0f;
+        if ((e = hipEventElapsedTime(&ms, slot.ev0, slot.ev1)) != hipSuccess) return hip_fail("hipEventElapsedTime", e);
+        g_scan_ms = ms;
+    }
     return int64_t(*slot.h);
 }
 
@@ -274,6 +308,16 @@ int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const 
 extern "C" {
 
 const char *ac_last_error(void) { return g_err.c_str(); }
+
+float ac_last_scan_ms(void) { return g_scan_ms; }
+
+int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t stream) {
+    if (!d_buf || !d_out || n < 0 || (n % 16) || (reinterpret_cast<uintptr_t>(d_buf) % 16))
+        return fail(AC_EINVAL, "ac_probe_read: buffer must be 16-byte aligned and a multiple of 16 bytes");
+    std::string err;
+    int rc = launch_probe_read(d_buf, n, d_out, stream, err);
+    return rc ? fail(rc, err) : AC_OK;
+}
 
 int ac_build_csr(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns, const ac_build_opts *opts,
                  ac_automaton **out) {
@@ -404,6 +448,8 @@ int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_b
         case AC_TABLE_OUT_OFF: src = P.out_off.data(); bytes = int64_t(P.out_off.size()) * 4; break;
         case AC_TABLE_OUT_PID: src = P.out_pid.data(); bytes = int64_t(P.out_pid.size()) * 4; break;
         case AC_TABLE_DEPTH: src = P.depth.data(); bytes = int64_t(P.depth.size()) * 4; break;
+        case AC_TABLE_PREFIX: src = P.ptab.data(); bytes = int64_t(P.ptab.size()) * 4; break;
+        case AC_TABLE_TAIL: src = P.tail.data(); bytes = int64_t(P.tail.size()) * 4; break;
         default:
             if (table > AC_TABLE_FILTER_BASE && table <= AC_TABLE_FILTER_BASE + kNumFilters) {
                 const auto &f = P.filter[table - AC_TABLE_FILTER_BASE - 1];

@@ -110,14 +110,38 @@ __device__ __forceinline__ int32_t step_global(const DevAut &A, const uint8_t *c
     return 0;
 }
 
-// Walks from offset o (relative to the start of the scanned buffer) and emits.
-__device__ void walk_from(const DevAut &A, const ScanArgs &S, const uint8_t *cls, int64_t o) {
-    int64_t end = S.n, tstart = 0;
-    int32_t tid = 0;
+// 24 x 24-bit product, low 32 bits, unsigned (__umul24 itself returns int,
+// whose right shift would sign-extend).
+__device__ __forceinline__ uint32_t hash24(uint32_t x, uint32_t mul) {
+    return static_cast<uint32_t>(__umul24(x, mul));
+}
+
+// Exact prefix lookup: {state at depth K | final bit} for the K-byte prefix x,
+// or 0 when no keyword starts with x.  The table is at most half full, so the
+// linear probe always meets an empty slot.
+template <typename Load>
+__device__ __forceinline__ uint32_t prefix_state(Load load, int bits, uint32_t x, uint32_t mul) {
+    const uint32_t mask = (1u << bits) - 1u;
+    const uint32_t key = x | 0x80000000u;
+    uint32_t slot = (hash24(x, mul) >> (32 - bits)) & mask;
+    while (true) {
+        const uint32_t k = load(2 * slot);
+        if (k == key) return load(2 * slot + 1);
+        if (k == 0u) return 0u;
+        slot = (slot + 1u) & mask;
+    }
+}
+
+// Text of a candidate offset: [start, end) of the text holding o and its id.
+__device__ __forceinline__ void locate_text(const ScanArgs &S, int64_t o, int64_t &tstart, int64_t &end,
+                                            int32_t &tid) {
+    tstart = 0;
+    end = S.n;
+    tid = 0;
     if (S.text_off) {
         // largest t with text_off[t] - text_off[0] <= o
         const int64_t base0 = S.text_off[0];
-        int32_t lo = 0, hi = S.n_texts;   // invariant: answer in [lo, hi)
+        int32_t lo = 0, hi = S.n_texts;   // answer in [lo, hi)
         while (hi - lo > 1) {
             const int32_t mid = (lo + hi) >> 1;
             if (S.text_off[mid] - base0 <= o) lo = mid;
@@ -127,12 +151,57 @@ __device__ void walk_from(const DevAut &A, const ScanArgs &S, const uint8_t *cls
         tstart = S.text_off[lo] - base0;
         end = min(S.text_off[lo + 1] - base0, S.n);
     }
-    int32_t s = 0;
-    for (int64_t j = o; j < end; ++j) {
-        const int32_t e = step_global(A, cls, s, S.text[j]);
-        if (e == 0) break;
-        s = e & 0x7fffffff;
-        if (e < 0) emit(A, S, o - tstart, tid, s);
+}
+
+// The walk of one candidate offset o (relative to the scanned buffer): the
+// first K transitions come from the exact prefix table, the rest from the
+// transition table; once the remaining path is forced (a unary chain to a
+// leaf with no keyword ending in between) the leaf's keyword is compared
+// with the text directly.  Emits every keyword starting at o.
+template <bool PT_LDS>
+__device__ void walk_candidate(const DevAut &A, const ScanArgs &S, const uint8_t *cls, const uint32_t *sptab,
+                               int64_t o) {
+    const int K = A.K;
+    if (o + K > S.n) return;
+    uint32_t x = 0;
+    for (int j = 0; j < K; ++j) x |= uint32_t(S.text[o + j]) << (8 * j);
+    uint32_t e;
+    if (PT_LDS) e = prefix_state([&](uint32_t i) { return sptab[i]; }, A.ptab_bits, x, A.hash_mul);
+    else e = prefix_state([&](uint32_t i) { return gload4(reinterpret_cast<const uint8_t *>(A.ptab + i)); },
+                          A.ptab_bits, x, A.hash_mul);
+    if (e == 0u) return;
+    int64_t tstart, end;
+    int32_t tid;
+    locate_text(S, o, tstart, end, tid);
+    if (o + K > end) return;
+    int32_t s = int32_t(e & 0x7fffffffu);
+    int64_t d = K;
+    if (e >> 31) emit(A, S, o - tstart, tid, s);
+    while (true) {
+        const int32_t t = A.tail[s];
+        if (t >= 0) {
+            if (t != s) {
+                const int32_t p = A.out_pid[A.out_off[t]];
+                const int32_t kb = A.kw_off[p];
+                const int64_t L = A.kw_off[p + 1] - kb;
+                if (o + L > end) return;
+                for (int64_t i = d; i < L; i += 16) {
+                    uint32_t diff = 0;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (i + u < L) diff |= uint32_t(S.text[o + i + u]) ^ uint32_t(A.kw_bytes[kb + i + u]);
+                    if (diff) return;
+                }
+                emit(A, S, o - tstart, tid, t);
+            }
+            return;
+        }
+        if (o + d >= end) return;
+        const int32_t e2 = step_global(A, cls, s, S.text[o + d]);
+        if (e2 == 0) return;
+        s = e2 & 0x7fffffff;
+        ++d;
+        if (e2 < 0) emit(A, S, o - tstart, tid, s);
     }
 }
 
@@ -204,7 +273,7 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
             const int w = s >> 2, r = s & 3;
             uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
             if (K < 3) x &= kmask;
-            const uint32_t p = __umul24(x, mul);
+            const uint32_t p = hash24(x, mul);
             uint32_t v;
             if (BITMAP) v = __builtin_amdgcn_ubfe(reinterpret_cast<const uint32_t *>(sfilt)[p >> shift], p, 1u);
             else v = sfilt[p >> shift];
@@ -220,6 +289,14 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
     __shared__ __align__(16) uint8_t scls[256];
+    constexpr int PT_SLOTS = FLOG2 >= 17 ? 2048 : 512;   // prefix-table slots that fit beside the filter
+    __shared__ __align__(16) uint32_t sptab[2 * PT_SLOTS];
+    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 9);
+    if (pt_lds) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.ptab);
+        uint4 *dst = reinterpret_cast<uint4 *>(sptab);
+        for (int i = threadIdx.x; i < (2 << A.ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
+    }
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[F.filter_kind - 1]);
         uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
@@ -249,7 +326,8 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         qlen -= take;
         if (lane < unsigned(take)) {
             const int64_t o = (qbase + int64_t(e >> 12) * qstride) * CH + int64_t(e & 4095u) - F.mis;
-            walk_from(A, S, scls, o);
+            if (pt_lds) walk_candidate<true>(A, S, scls, sptab, o);
+            else walk_candidate<false>(A, S, scls, sptab, o);
         }
     };
     auto push = [&](unsigned long long m, uint32_t k) {
@@ -353,6 +431,19 @@ __global__ void zero_kernel(unsigned long long *count, int64_t *per_text, int32_
     if (per_text && i < n_texts) per_text[i] = 0;
 }
 
+// Achievable-bandwidth probe: every lane streams 16-byte words and folds them
+// into one value, written once per wave so the loads cannot be dropped.
+__global__ __launch_bounds__(256) void probe_read_kernel(const uint8_t *buf, int64_t n16, uint32_t *out) {
+    uint32_t acc = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride) {
+        const u32x4 v = gload16(buf + i * 16);
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    for (int d = 32; d >= 1; d >>= 1) acc ^= __shfl_xor(acc, d);
+    if (lane_id() == 0 && acc == 0x9E3779B9u) *out = acc;   // practically never taken
+}
+
 using FilteredFn = void (*)(const DevAut, const ScanArgs, const FilterLaunch);
 
 template <int K, bool BM, int FLOG2>
@@ -381,7 +472,8 @@ FilteredFn pick_filtered(int K, int kind, int segs) {
 }
 
 int64_t filtered_lds(const FilterGeom &g) {
-    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + 256;
+    const int64_t pt_slots = g.bytes > (64 << 10) ? 2048 : 512;
+    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + 256 + pt_slots * 8;
 }
 
 std::mutex g_attr_mu;
@@ -413,7 +505,8 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
             g = filter_geom(cfg.filter);
         }
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
-        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = 4;
+        // the bit maps need more registers: two segments keep them spill-free
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = g.bitmap ? 2 : 4;
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
     } else {
@@ -423,6 +516,19 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         if (cfg.table_in_lds == 1 && !fits) cfg.table_in_lds = 2;
         if (cfg.table_in_lds != 1 && cfg.table_in_lds != 2) cfg.table_in_lds = fits ? 1 : 2;
     }
+}
+
+int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t stream, std::string &err) {
+    if (n <= 0) return AC_OK;
+    int dev = 0, cus = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t n16 = n / 16;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n16 + 255) / 256, int64_t(cus) * 8));
+    probe_read_kernel<<<unsigned(grid), 256, 0, stream>>>(buf, n16, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { err = std::string("probe launch: ") + hipGetErrorString(e); return AC_EHIP; }
+    return AC_OK;
 }
 
 int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts, hipStream_t stream,

@@ -56,6 +56,11 @@ struct Plan {
     uint32_t hash_mul = kDefaultHashMul;
     int32_t n_prefixes = 0;
     std::vector<uint8_t> filter[kNumFilters];   // indexed by kind - 1
+    int32_t ptab_bits = 0;
+    std::vector<uint32_t> ptab;    // [2 << ptab_bits]: {prefix | valid, state | final}
+    std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1
+    std::vector<uint8_t> kw_bytes; // keywords back to back
+    std::vector<int32_t> kw_off;   // [n + 1]
     double build_ms = 0.0;
 };
 
@@ -68,7 +73,12 @@ struct DevAut {
     const uint8_t *label;
     const int32_t *out_off;
     const int32_t *out_pid;
+    const uint32_t *ptab;          // exact prefix table (global copy)
+    const int32_t *tail;
+    const uint8_t *kw_bytes;
+    const int32_t *kw_off;
     int32_t C, S, S_dense, K, max_len;
+    int32_t ptab_bits;
     uint32_t hash_mul;
 };
 
@@ -114,4 +124,5 @@ int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cf
 int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
                 hipStream_t stream, std::string &err);
 void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg);
+int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t stream, std::string &err);
 }  // namespace pfac

@@ -221,6 +221,54 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             }
         }
     }
+    // ---- exact prefix table: K-byte prefix -> state at depth K ------------
+    // Open addressing with linear probing, at most half full, probed from
+    // the same product as the filters.  Slot = {prefix | valid bit, state |
+    // final bit}; a zero key marks an empty slot.
+    {
+        int bits = 6;
+        while ((int64_t(1) << bits) < 2 * int64_t(P.n_prefixes)) ++bits;
+        P.ptab_bits = bits;
+        const uint32_t mask = (1u << bits) - 1u;
+        P.ptab.assign(size_t(2) << bits, 0u);
+        for (int32_t p = 0; p < n; ++p) {
+            uint32_t x = 0;
+            for (int j = 0; j < P.K; ++j) x |= uint32_t(kw(p)[j]) << (8 * j);
+            int32_t s = 0;   // follow the trie for K bytes
+            for (int j = 0; j < P.K; ++j) {
+                const uint8_t b = kw(p)[j];
+                int32_t lo = P.first_child[size_t(s)], hi = lo + P.n_child[size_t(s)];
+                while (lo < hi && P.label[size_t(lo)] != b) ++lo;
+                s = lo;
+            }
+            uint32_t slot = prefix_hash(x, mul) >> (32 - bits);
+            while (P.ptab[size_t(slot) * 2] != 0u && P.ptab[size_t(slot) * 2] != (x | 0x80000000u))
+                slot = (slot + 1u) & mask;
+            P.ptab[size_t(slot) * 2] = x | 0x80000000u;
+            P.ptab[size_t(slot) * 2 + 1] = uint32_t(s) | (is_final(s) ? 0x80000000u : 0u);
+        }
+    }
+
+    // ---- unary tails: state -> leaf when the rest of the path is forced -----
+    // tail[s] = leaf l when every state from s down to l has one child and no
+    // state strictly between s and l ends a keyword; the remaining bytes can
+    // then be compared with the leaf's keyword in one pass.  -1 otherwise.
+    P.tail.assign(size_t(S), -1);
+    for (int32_t s = S - 1; s >= 0; --s) {
+        const int32_t nc = P.n_child[size_t(s)];
+        if (nc == 0) {
+            P.tail[size_t(s)] = s;
+        } else if (nc == 1) {
+            const int32_t c = P.first_child[size_t(s)];
+            if (P.n_child[size_t(c)] == 0) P.tail[size_t(s)] = c;
+            else if (!is_final(c)) P.tail[size_t(s)] = P.tail[size_t(c)];
+        }
+    }
+    // keyword bytes (for tail comparisons) with int32 offsets
+    P.kw_bytes.assign(bytes + offsets[0], bytes + offsets[0] + total);
+    P.kw_off.resize(size_t(n) + 1);
+    for (int32_t p = 0; p <= n; ++p) P.kw_off[size_t(p)] = int32_t(offsets[p] - offsets[0]);
+
     P.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return AC_OK;
 }

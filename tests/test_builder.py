@@ -1,0 +1,225 @@
+"""Host-side checks of the GPU library's automaton builder (no GPU needed).
+
+``ac_compile`` runs every host step of ``ac_build``; its tables are exported
+and walked here by a small test-side walker to check the invariants the
+kernels rely on.  The CPU oracle is not involved: these are properties of the
+built tables themselves (trie size, keyword paths, layouts, prefix table,
+forced-path tails, filters), plus the C-ABI surface.
+"""
+
+import ctypes
+import dataclasses
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1412_7789_amd as pf
+from paper_1412_7789_amd import _lib as L
+from workloads import SPECS, make_keywords
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    if not os.path.exists(pf.LIB_PATH):
+        from paper_1412_7789_amd.build import build
+        build()
+    return pf.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pfac.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ac_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 16
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(L.EXPORTS) == names
+
+
+class Tables:
+    def __init__(self, kws, budget=0):
+        self.plan = pf.Plan(kws, dense_budget_bytes=budget)
+        self.info = self.plan.info()
+        e = self.plan.export
+        self.cls = e(L.AC_TABLE_CLASS_MAP, np.uint8)
+        self.dense = e(L.AC_TABLE_DENSE, np.int32)
+        self.node = e(L.AC_TABLE_NODE, np.int32)
+        self.label = e(L.AC_TABLE_LABEL, np.uint8)
+        self.out_off = e(L.AC_TABLE_OUT_OFF, np.int32)
+        self.out_pid = e(L.AC_TABLE_OUT_PID, np.int32)
+        self.depth = e(L.AC_TABLE_DEPTH, np.int32)
+        self.ptab = e(L.AC_TABLE_PREFIX, np.uint32)
+        self.tail = e(L.AC_TABLE_TAIL, np.int32)
+        self.C = self.info["n_classes"]
+        self.S = self.info["n_states"]
+        self.Sd = self.info["n_dense_states"]
+
+    def step(self, s, b):
+        """(next state, final) or None, read from the built layout."""
+        if s < self.Sd:
+            e = int(self.dense[s * self.C + int(self.cls[b])])
+            if e == 0:
+                return None
+            return e & 0x7FFFFFFF, e < 0
+        r = s - self.Sd
+        fc, nc = int(self.node[2 * r]), int(self.node[2 * r + 1]) & 0x7FFFFFFF
+        for t in range(fc, fc + nc):
+            if self.label[t] == b:
+                return t, int(self.node[2 * (t - self.Sd) + 1]) < 0
+        return None
+
+    def children(self, s):
+        return [t for b in range(256) for t in [self.step(s, b)] if t is not None]
+
+    def outputs(self, s):
+        return self.out_pid[self.out_off[s]:self.out_off[s + 1]].tolist()
+
+
+def kw_sets():
+    rng = np.random.default_rng(2)
+    yield "fig4", [b"AB", b"ABG", b"BEDE", b"ED"]
+    yield "nested", [b"a", b"ab", b"abc", b"bc", b"c", b"abc"]
+    yield "tiny", make_keywords(SPECS["tiny"], np.random.default_rng(0), np.random.default_rng(1))
+    yield "bytes", [bytes(rng.integers(0, 256, size=int(L), dtype=np.uint8)) for L in rng.integers(1, 9, size=300)]
+    yield "shared", make_keywords(dataclasses.replace(SPECS["large"], n=500),
+                                  np.random.default_rng(3), np.random.default_rng(4))
+
+
+@pytest.mark.parametrize("name,kws", list(kw_sets()))
+@pytest.mark.parametrize("budget", [0, 1])
+def test_trie_paths_outputs_and_layouts(name, kws, budget):
+    T = Tables(kws, budget)
+    prefixes = {k[:i] for k in kws for i in range(len(k) + 1)}
+    assert T.S == len(prefixes)
+    if budget == 1:
+        assert T.Sd == 1          # only the root row is dense; every other state is compact
+    # each keyword's path ends at a state whose outputs contain its id
+    for p, k in enumerate(kws):
+        s = 0
+        for j, b in enumerate(k):
+            nxt = T.step(s, b)
+            assert nxt is not None, (name, p, j)
+            s, fin = nxt
+            assert fin == (k[:j + 1] in set(kws))
+        assert p in T.outputs(s)
+        assert T.depth[s] == len(k)
+    # outputs partition the ids, ascending per state
+    allp = sorted(T.out_pid.tolist())
+    assert allp == list(range(len(kws)))
+    for s in range(T.S):
+        o = T.outputs(s)
+        assert o == sorted(o)
+    # breadth-first numbering: depths non-decreasing
+    assert (np.diff(T.depth) >= 0).all()
+
+
+def test_dense_and_compact_layouts_agree():
+    rng = np.random.default_rng(9)
+    kws = [bytes(rng.integers(97, 101, size=int(L), dtype=np.uint8)) for L in rng.integers(1, 10, size=200)]
+    full, compact = Tables(kws, 0), Tables(kws, 1)
+    assert full.Sd == full.S and compact.Sd == 1
+    for s in range(full.S):
+        for b in list(range(96, 102)) + [0, 255]:
+            assert full.step(s, b) == compact.step(s, b), (s, b)
+
+
+def test_class_map():
+    T = Tables([b"abc", b"zz"])
+    used = {ord(c) for c in "abcz"}
+    assert T.C == len(used) + 1
+    assert sorted(int(T.cls[b]) for b in used) == list(range(1, len(used) + 1))
+    assert all(T.cls[b] == 0 for b in range(256) if b not in used)
+    T = Tables([bytes([b]) for b in range(256)])
+    assert T.C == 256 and (T.cls == np.arange(256)).all()
+
+
+@pytest.mark.parametrize("name,kws", list(kw_sets()))
+def test_prefix_table_and_tails(name, kws):
+    T = Tables(kws)
+    K = T.info["prefix_len"]
+    assert K == min(3, min(len(k) for k in kws))
+
+    def walk(prefix):
+        s = 0
+        for b in prefix:
+            nxt = T.step(s, b)
+            if nxt is None:
+                return None
+            s = nxt[0]
+        return s
+
+    def lookup(x):
+        bits = int(np.log2(len(T.ptab) // 2))
+        slot = T.plan.hash(x) >> (32 - bits)
+        while True:
+            k, v = int(T.ptab[2 * slot]), int(T.ptab[2 * slot + 1])
+            if k == (x | 0x80000000):
+                return v
+            if k == 0:
+                return 0
+            slot = (slot + 1) % (len(T.ptab) // 2)
+
+    keyset = set(kws)
+    pref = {k[:K] for k in kws}
+    assert T.info["n_prefixes"] == len(pref)
+    for pr in pref:
+        x = int.from_bytes(pr, "little")
+        v = lookup(x)
+        s = walk(pr)
+        assert v & 0x7FFFFFFF == s
+        assert bool(v >> 31) == (pr in keyset)
+    # values that start no keyword are absent
+    rng = np.random.default_rng(1)
+    for x in rng.integers(0, 1 << (8 * K), size=2000):
+        pr = int(x).to_bytes(K, "little")
+        if pr not in pref:
+            assert lookup(int(x)) == 0
+    # tails: tail[s] = leaf reached by a forced path with no keyword ending strictly between
+    for s in range(T.S):
+        path, t = [s], s
+        while True:
+            ch = T.children(t)
+            if len(ch) != 1:
+                break
+            t, fin = ch[0]
+            path.append(t)
+            if fin and T.children(t):
+                t = None
+                break
+        leaf = t if (t is not None and not T.children(t)) else None
+        assert T.tail[s] == (leaf if leaf is not None else -1), s
+
+
+def test_filters_have_no_false_negatives():
+    kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
+    T = Tables(kws)
+    K = T.info["prefix_len"]
+    geoms = {1: (False, 17), 2: (True, 17), 3: (False, 16), 4: (True, 16)}
+    for kind, (bitmap, flog2) in geoms.items():
+        f = T.plan.export(L.AC_TABLE_FILTER_BASE + kind, np.uint8)
+        assert len(f) == 1 << flog2
+        for k in kws:
+            h = T.plan.hash(int.from_bytes(k[:K], "little"))
+            if bitmap:
+                w = f.view(np.uint32)[h >> (32 - (flog2 - 2))]
+                assert (int(w) >> (h & 31)) & 1
+            else:
+                assert f[h >> (32 - flog2)] == 1
+
+
+def test_build_errors(lib):
+    with pytest.raises(pf.PfacError):
+        pf.Plan([b"a", b""])
+    h = ctypes.c_void_p()
+    assert lib.ac_compile(None, None, 0, None, ctypes.byref(h)) == L.AC_EINVAL
+    assert b"keyword" in lib.ac_last_error()
+    # a NULL automaton is rejected before any GPU call
+    assert lib.ac_match(None, None, 0, None, None) == L.AC_EINVAL

@@ -1,0 +1,188 @@
+"""GPU parity on the benchmark workloads, at their real sizes.
+
+* sweep (1000 printable keywords): every size of the x16 sweep up to 64 MiB
+  compared in full with the oracle; 1 GiB (the benchmark's launch
+  configuration) checked on exact oracle windows plus soundness of every match
+  and completeness of every surviving plant.
+* large automaton (20000 byte keywords, ~734k states, compact layout): 64 MiB
+  in full, 1 GiB by windows.
+* batched (2000 keywords, 4096 log-normal texts): every text against the
+  oracle, and the batch against per-text calls.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from tests.helpers import as_pairs, assert_same
+from workloads import GIB, MIB, config_batched, config_large_automaton, config_sweep
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+pf = None
+
+
+def setup_module(module):
+    global pf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1412_7789_amd as _pf
+    _pf.load()
+    pf = _pf
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(a, text_np, launch=None):
+    t = torch.from_numpy(text_np).cuda()
+    off, pid = a.match(t, launch=launch)
+    res = (off.cpu().numpy(), pid.cpu().numpy())
+    del t
+    return res
+
+
+def check_sound(keywords, text, off, pid):
+    """Every reported (o, p) really is an occurrence (vectorised per keyword)."""
+    for p in np.unique(pid):
+        k = np.frombuffer(keywords[p], dtype=np.uint8)
+        o = off[pid == p]
+        assert (o >= 0).all() and (o + len(k) <= len(text)).all()
+        win = text[o[:, None] + np.arange(len(k))[None, :]]
+        assert (win == k[None, :]).all(), f"unsound match for keyword {p}"
+
+
+def check_windows(keywords, text, off, pid, n_windows=6, width=4 * MIB, seed=0):
+    """Exact comparison on oracle windows: the GPU matches lying wholly inside
+    a window equal the oracle's result on that window."""
+    rng = np.random.default_rng(seed)
+    lens = np.array([len(k) for k in keywords], dtype=np.int64)
+    o_or = Oracle(keywords)
+    starts = [0, len(text) - width] + list(rng.integers(0, len(text) - width, size=n_windows - 2))
+    for w0 in starts:
+        w1 = w0 + width
+        eo, ep = o_or.match(text[w0:w1])
+        sel = (off >= w0) & (off + lens[pid] <= w1)
+        assert_same((off[sel] - w0, pid[sel]), (eo, ep), f"window {w0}")
+    o_or.close()
+
+
+def check_plants(keywords, text, off, pid, plants):
+    got = set(zip(off.tolist(), pid.tolist()))
+    for o, p in plants:
+        k = keywords[p]
+        if bytes(text[o:o + len(k)]) == k:
+            assert (o, p) in got
+
+
+@pytest.mark.parametrize("size", [1 << 10, 1 << 14, 1 << 18, 1 << 22, 1 << 26])
+def test_sweep_sizes_full(size):
+    w = config_sweep(size)
+    a = pf.Automaton(w.keywords)
+    say("sweep", size)
+    assert_same(run_gpu(a, w.text), Oracle(w.keywords).match(w.text), f"sweep {size}")
+
+
+def test_sweep_policies_agree():
+    w = config_sweep(1 << 22)
+    a = pf.Automaton(w.keywords)
+    exp = Oracle(w.keywords).match(w.text)
+    for cfg in [dict(policy=1, filter=f, segs=s, block=b) for f in (1, 2, 3, 4) for s in (1, 2, 4)
+                for b in (256, 1024)] + [dict(policy=2)]:
+        say("sweep policy", cfg)
+        assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
+
+
+def test_sweep_1gib_launch():
+    w = config_sweep(GIB)
+    a = pf.Automaton(w.keywords)
+    say("sweep 1 GiB", a.default_launch(GIB))
+    off, pid = run_gpu(a, w.text)
+    off, pid = as_pairs(off, pid)
+    assert len(off) > 250_000
+    check_sound(w.keywords, w.text, off, pid)
+    check_plants(w.keywords, w.text, off, pid, w.plants)
+    check_windows(w.keywords, w.text, off, pid)
+
+
+def test_large_automaton_64mib_full():
+    w = config_large_automaton(64 * MIB)
+    a = pf.Automaton(w.keywords)
+    info = a.info()
+    say("large 64 MiB", info["n_states"], info["n_dense_states"])
+    assert info["n_dense_states"] < info["n_states"]      # compact layout in use
+    exp = Oracle(w.keywords).match(w.text)
+    assert_same(run_gpu(a, w.text), exp, "large 64 MiB")
+    for cfg in [dict(policy=1, filter=1), dict(policy=1, filter=4, segs=1), dict(policy=2)]:
+        say("large policy", cfg)
+        assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
+
+
+def test_large_automaton_1gib_launch():
+    w = config_large_automaton(GIB)
+    a = pf.Automaton(w.keywords)
+    say("large 1 GiB")
+    off, pid = run_gpu(a, w.text)
+    off, pid = as_pairs(off, pid)
+    check_sound(w.keywords, w.text, off, pid)
+    check_plants(w.keywords, w.text, off, pid, w.plants)
+    check_windows(w.keywords, w.text, off, pid, n_windows=4)
+
+
+def batch_expected(keywords, texts, offsets):
+    o = Oracle(keywords)
+    tids, offs, pids = [], [], []
+    for t in range(len(offsets) - 1):
+        eo, ep = o.match(texts[offsets[t]:offsets[t + 1]])
+        tids.append(np.full(len(eo), t, dtype=np.int64))
+        offs.append(eo)
+        pids.append(ep)
+    o.close()
+    return np.concatenate(tids), np.concatenate(offs), np.concatenate(pids)
+
+
+def batch_key(tid, off, pid):
+    # one int64 per match for set comparison: (text id, offset, keyword id)
+    return np.sort((np.asarray(tid, np.int64) << 44) | (np.asarray(off, np.int64) << 16) | np.asarray(pid, np.int64))
+
+
+def test_batched_config_every_text():
+    w = config_batched()
+    a = pf.Automaton(w.keywords)
+    say("batched", len(w.offsets) - 1, int(w.offsets[-1]))
+    d_texts = torch.from_numpy(w.texts).cuda()
+    d_offs = torch.from_numpy(w.offsets).cuda()
+    tid, off, pid, per = a.match_batch(d_texts, d_offs)
+    tid, off, pid, per = (x.cpu().numpy() for x in (tid, off, pid, per))
+    et, eo, ep = batch_expected(w.keywords, w.texts, w.offsets)
+    assert len(tid) == len(et)
+    assert (batch_key(tid, off, pid) == batch_key(et, eo, ep)).all()
+    assert (per == np.bincount(et, minlength=len(w.offsets) - 1)).all()
+    # the same texts scanned alone give the same matches
+    rng = np.random.default_rng(0)
+    for t in rng.choice(len(w.offsets) - 1, size=40, replace=False):
+        s, e = int(w.offsets[t]), int(w.offsets[t + 1])
+        alone = run_gpu(a, w.texts[s:e])
+        sel = tid == t
+        assert_same(alone, (off[sel], pid[sel]), f"text {t} alone vs batch")
+
+
+def test_batch_edge_cases():
+    kws = [b"abc", b"abcd", b"bcd", b"zz", b"a"]
+    texts = [b"", b"a", b"ab", b"abcd", b"", b"zzz", b"xabcdx" * 50, b"a" * 3, b"", b"bcd"]
+    flat = np.frombuffer(b"".join(texts), dtype=np.uint8).copy()
+    offs = np.zeros(len(texts) + 1, dtype=np.int64)
+    np.cumsum([len(t) for t in texts], out=offs[1:])
+    a = pf.Automaton(kws)
+    for shift in (0, 1, 5):          # unaligned packed buffers
+        buf = np.zeros(len(flat) + shift, dtype=np.uint8)
+        buf[shift:] = flat
+        d = torch.from_numpy(buf).cuda()[shift:]
+        tid, off, pid, per = (x.cpu().numpy() for x in a.match_batch(d, torch.from_numpy(offs).cuda()))
+        et, eo, ep = batch_expected(kws, flat, offs)
+        assert (batch_key(tid, off, pid) == batch_key(et, eo, ep)).all(), shift
+        assert (per == np.bincount(et, minlength=len(texts))).all()

@@ -22,4 +22,7 @@ from .gen import (  # noqa: F401
     config_served,
     paper_workload,
     SWEEP_SIZES,
+    KIB,
+    MIB,
+    GIB,
 )
