@@ -35,15 +35,35 @@ struct CountSlot {
     unsigned long long *d = nullptr;
     unsigned long long *h = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // scan timing, created on first use
+    HitScratch hs;                             // hit regions of the filtered policy
 };
 std::mutex g_slots_mu;
 std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
 
-int count_slot(int device, hipStream_t stream, CountSlot &out) {
+// Grows the slot's hit regions to at least `regions` (never shrinks).
+int ensure_hits(CountSlot &s, int64_t regions) {
+    if (s.hs.regions >= regions) return AC_OK;
+    if (s.hs.hits) (void)hipFree(s.hs.hits);
+    if (s.hs.count) (void)hipFree(s.hs.count);
+    s.hs = HitScratch();
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.hs.hits), size_t(regions) * kHitCap * sizeof(uint4));
+    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit regions): ") + hipGetErrorString(e));
+    e = hipMalloc(reinterpret_cast<void **>(&s.hs.count), size_t(regions) * sizeof(int32_t));
+    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit counts): ") + hipGetErrorString(e));
+    s.hs.regions = regions;
+    s.hs.cap = kHitCap;
+    return AC_OK;
+}
+
+int count_slot(int device, hipStream_t stream, CountSlot &out, int64_t regions) {
     std::lock_guard<std::mutex> lk(g_slots_mu);
     auto key = std::make_pair(device, stream);
     auto it = g_slots.find(key);
-    if (it != g_slots.end()) { out = it->second; return AC_OK; }
+    if (it != g_slots.end()) {
+        int rc = ensure_hits(it->second, regions);
+        out = it->second;
+        return rc;
+    }
     CountSlot s;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
@@ -51,9 +71,10 @@ int count_slot(int device, hipStream_t stream, CountSlot &out) {
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
     if ((e = hipEventCreate(&s.ev0)) != hipSuccess || (e = hipEventCreate(&s.ev1)) != hipSuccess)
         return hip_fail("hipEventCreate", e);
+    int rc = ensure_hits(s, regions);
     g_slots[key] = s;
     out = s;
-    return AC_OK;
+    return rc;
 }
 
 int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -93,6 +114,7 @@ int upload(ac_automaton *a) {
     Sec opid{P.out_pid.data(), int64_t(P.out_pid.size()) * 4, 0};
     Sec ptab{P.ptab.data(), int64_t(P.ptab.size()) * 4, 0};
     Sec tail{P.tail.data(), int64_t(P.tail.size()) * 4, 0};
+    Sec tinfo{P.tailinfo.data(), int64_t(P.tailinfo.size()) * 4, 0};
     Sec kwb{P.kw_bytes.data(), int64_t(P.kw_bytes.size()), 0};
     Sec kwo{P.kw_off.data(), int64_t(P.kw_off.size()) * 4, 0};
     int64_t at = 0;
@@ -103,12 +125,12 @@ int upload(ac_automaton *a) {
         place(filt[k]);
     }
     place(dense); place(node); place(label); place(ooff); place(opid);
-    place(ptab); place(tail); place(kwb); place(kwo);
+    place(ptab); place(tail); place(tinfo); place(kwb); place(kwo);
     a->dbytes = at;
     std::vector<uint8_t> staging(size_t(at), 0);
     auto copy = [&](const Sec &s) { if (s.bytes) std::memcpy(staging.data() + s.at, s.src, size_t(s.bytes)); };
     copy(cls); for (auto &f : filt) copy(f); copy(dense); copy(node); copy(label); copy(ooff); copy(opid);
-    copy(ptab); copy(tail); copy(kwb); copy(kwo);
+    copy(ptab); copy(tail); copy(tinfo); copy(kwb); copy(kwo);
     e = hipMalloc(&a->dmem, size_t(at));
     if (e != hipSuccess) { a->dmem = nullptr; return fail(AC_ENOMEM, std::string("hipMalloc(automaton): ") + hipGetErrorString(e)); }
     e = hipMemcpy(a->dmem, staging.data(), size_t(at), hipMemcpyHostToDevice);
@@ -124,6 +146,7 @@ int upload(ac_automaton *a) {
     D.out_pid = reinterpret_cast<const int32_t *>(b + opid.at);
     D.ptab = reinterpret_cast<const uint32_t *>(b + ptab.at);
     D.tail = reinterpret_cast<const int32_t *>(b + tail.at);
+    D.tailinfo = reinterpret_cast<const int4 *>(b + tinfo.at);
     D.kw_bytes = b + kwb.at;
     D.kw_off = reinterpret_cast<const int32_t *>(b + kwo.at);
     D.ptab_bits = P.ptab_bits;
@@ -151,7 +174,8 @@ void fill_info(const Plan &P, ac_info_t *o) {
     o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
     o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;
     o->prefix_table_bytes = int64_t(P.ptab.size()) * 4;
-    o->tail_bytes = int64_t(P.tail.size()) * 4 + int64_t(P.kw_bytes.size()) + int64_t(P.kw_off.size()) * 4;
+    o->tail_bytes = int64_t(P.tail.size() + P.tailinfo.size()) * 4 + int64_t(P.kw_bytes.size()) +
+                    int64_t(P.kw_off.size()) * 4;
     for (const auto &f : P.filter) o->filter_bytes += int64_t(f.size());
     o->device_bytes = 256 + o->dense_bytes + o->compact_bytes + o->output_bytes + o->filter_bytes +
                       o->prefix_table_bytes + o->tail_bytes;
@@ -180,12 +204,15 @@ int device_matches(const ac_automaton *a) {
 }
 
 // Enqueue zero + scan for one text or a batch.
-int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch,
-            unsigned long long *d_count, hipStream_t stream, const CountSlot *timing = nullptr) {
+ac_launch resolved(const ac_automaton *a, const ScanArgs &S, const ac_launch *launch, bool batch) {
     ac_launch cfg{};
     if (launch) cfg = *launch;
-    if (batch && cfg.policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
     resolve_launch(a, S.n, batch, cfg);
+    return cfg;
+}
+
+int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch &cfg, bool batch, unsigned long long *d_count,
+            const HitScratch &hs, hipStream_t stream, const CountSlot *timing = nullptr) {
     S.count = d_count;
     std::string err;
     int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
@@ -194,7 +221,7 @@ int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool bat
         hipError_t e = hipEventRecord(timing->ev0, stream);
         if (e != hipSuccess) return hip_fail("hipEventRecord", e);
     }
-    rc = launch_scan(a, S, cfg, stream, err);
+    rc = launch_scan(a, S, cfg, hs, stream, err);
     if (rc) return fail(rc, err);
     if (timing) {
         hipError_t e = hipEventRecord(timing->ev1, stream);
@@ -204,12 +231,14 @@ int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool bat
 }
 
 int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch, hipStream_t stream) {
+    if (batch && launch && launch->policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
+    const ac_launch cfg = resolved(a, S, launch, batch);
     CountSlot slot;
-    int rc = count_slot(a->device, stream, slot);
+    int rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg));
     if (rc) return rc;
     const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN);
     g_scan_ms = -1.0f;
-    rc = enqueue(a, S, launch, batch, slot.d, stream, timed ? &slot : nullptr);
+    rc = enqueue(a, S, cfg, batch, slot.d, slot.hs, stream, timed ? &slot : nullptr);
     if (rc) return rc;
     hipError_t e = hipMemcpyAsync(slot.h, slot.d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
@@ -384,8 +413,11 @@ int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len, co
     if (rc) return rc;
     if ((rc = check_launch(launch))) return rc;
     if (!d_count) return fail(AC_EINVAL, "ac_match_async: NULL count pointer");
-    return enqueue(a, single_args(d_text, len, matches), launch, false,
-                   reinterpret_cast<unsigned long long *>(d_count), stream);
+    const ScanArgs S = single_args(d_text, len, matches);
+    const ac_launch cfg = resolved(a, S, launch, false);
+    CountSlot slot;
+    if ((rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    return enqueue(a, S, cfg, false, reinterpret_cast<unsigned long long *>(d_count), slot.hs, stream);
 }
 
 int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets,
@@ -405,8 +437,12 @@ int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts, const in
     if (rc) return rc;
     if ((rc = check_launch(launch))) return rc;
     if (!d_count) return fail(AC_EINVAL, "ac_match_batch_async: NULL count pointer");
-    return enqueue(a, batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches), launch, true,
-                   reinterpret_cast<unsigned long long *>(d_count), stream);
+    if (launch && launch->policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
+    const ScanArgs S = batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches);
+    const ac_launch cfg = resolved(a, S, launch, true);
+    CountSlot slot;
+    if ((rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    return enqueue(a, S, cfg, true, reinterpret_cast<unsigned long long *>(d_count), slot.hs, stream);
 }
 
 // ---- host-side inspection -----------------------------------------------------

@@ -36,8 +36,14 @@ namespace pfac {
 
 namespace {
 
-constexpr int kQueueCap = 128;   // per-wave candidate queue (entries)
+constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
+constexpr int kDrain = 192;      // candidates taken per drain (3 per lane)
+constexpr int kWalkBlock = 512;  // threads of the walk kernel per hit region
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
+
+__device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t lmin(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t lmax(int64_t a, int64_t b) { return a > b ? a : b; }
 
 __device__ __forceinline__ unsigned lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -62,6 +68,17 @@ typedef const __attribute__((address_space(1))) uint32_t global_u32;
 
 __device__ __forceinline__ u32x4 gload16(const uint8_t *p) { return *(global_u32x4 *)(p); }
 __device__ __forceinline__ uint32_t gload4(const uint8_t *p) { return *(global_u32 *)(p); }
+__device__ __forceinline__ uint32_t gload1(const uint8_t *p) {
+    return *(const __attribute__((address_space(1))) uint8_t *)(p);
+}
+__device__ __forceinline__ void gstore16(uint4 *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    u32x4 v;
+    v.x = a;
+    v.y = b;
+    v.z = c;
+    v.w = d;
+    *(__attribute__((address_space(1))) u32x4 *)(p) = v;
+}
 
 // Orders LDS traffic between lanes of one wave (queue producer -> consumer).
 __device__ __forceinline__ void wave_sync() {
@@ -89,6 +106,57 @@ __device__ void emit(const DevAut &A, const ScanArgs &S, int64_t off, int32_t ti
             if (S.out_tid) S.out_tid[idx] = tid;
         }
         if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
+    }
+}
+
+// Block-level staging of matches in LDS: one global atomic per block instead
+// of one per match.  Matches beyond the stage's capacity go straight out
+// through emit().
+constexpr int kStageCap = 1024;
+struct MatchStage {
+    int64_t off[kStageCap];
+    int32_t pid[kStageCap];
+    int32_t tid[kStageCap];
+    int32_t n;
+    unsigned long long base;
+};
+
+__device__ __forceinline__ void emit_staged(const DevAut &A, const ScanArgs &S, MatchStage *st, int64_t off,
+                                            int32_t tid, int32_t s) {
+    const int32_t k0 = A.out_off[s], k1 = A.out_off[s + 1];
+    for (int32_t k = k0; k < k1; ++k) {
+        const int32_t i = atomicAdd(&st->n, 1);
+        if (i < kStageCap) {
+            st->off[i] = off;
+            st->pid[i] = A.out_pid[k];
+            st->tid[i] = tid;
+            if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
+        } else {
+            // stage full: this id goes out directly (one atomic)
+            const unsigned long long idx = atomicAdd(S.count, 1ull);
+            if (idx < static_cast<unsigned long long>(S.cap)) {
+                S.out_off[idx] = off;
+                S.out_pid[idx] = A.out_pid[k];
+                if (S.out_tid) S.out_tid[idx] = tid;
+            }
+            if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
+        }
+    }
+}
+
+// Called by every thread of the block once all its walks are done.
+__device__ __forceinline__ void flush_stage(const ScanArgs &S, MatchStage *st) {
+    __syncthreads();
+    const int32_t n = imin(st->n, kStageCap);
+    if (threadIdx.x == 0) st->base = n ? atomicAdd(S.count, static_cast<unsigned long long>(n)) : 0ull;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const unsigned long long idx = st->base + unsigned(i);
+        if (idx < static_cast<unsigned long long>(S.cap)) {
+            S.out_off[idx] = st->off[i];
+            S.out_pid[idx] = st->pid[i];
+            if (S.out_tid) S.out_tid[idx] = st->tid[i];
+        }
     }
 }
 
@@ -149,60 +217,77 @@ __device__ __forceinline__ void locate_text(const ScanArgs &S, int64_t o, int64_
         }
         tid = lo;
         tstart = S.text_off[lo] - base0;
-        end = min(S.text_off[lo + 1] - base0, S.n);
+        end = lmin(S.text_off[lo + 1] - base0, S.n);
     }
 }
 
-// The walk of one candidate offset o (relative to the scanned buffer): the
-// first K transitions come from the exact prefix table, the rest from the
-// transition table; once the remaining path is forced (a unary chain to a
-// leaf with no keyword ending in between) the leaf's keyword is compared
-// with the text directly.  Emits every keyword starting at o.
-template <bool PT_LDS>
-__device__ void walk_candidate(const DevAut &A, const ScanArgs &S, const uint8_t *cls, const uint32_t *sptab,
-                               int64_t o) {
+// The rest of the walk from offset o (relative to the scanned buffer) once
+// the exact prefix table gave e = {state at depth K | final bit}: further
+// transitions come from the transition table, and once the remaining path is
+// forced (a unary chain to a leaf with no keyword ending in between) the
+// leaf's keyword is compared with the text directly.  With REC, rb holds the
+// 8 text bytes that follow the prefix (as captured by the streaming kernel),
+// so most walks end without reading the text again.  Emits every keyword
+// starting at o.
+template <bool REC, bool STAGED>
+__device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, const uint8_t *cls, int64_t o,
+                                          uint32_t e, uint2 rb, MatchStage *st) {
+    auto out = [&](int64_t off, int32_t tid, int32_t state) __attribute__((always_inline)) {
+        if (STAGED) emit_staged(A, S, st, off, tid, state);
+        else emit(A, S, off, tid, state);
+    };
     const int K = A.K;
-    if (o + K > S.n) return;
-    uint32_t x = 0;
-    for (int j = 0; j < K; ++j) x |= uint32_t(S.text[o + j]) << (8 * j);
-    uint32_t e;
-    if (PT_LDS) e = prefix_state([&](uint32_t i) { return sptab[i]; }, A.ptab_bits, x, A.hash_mul);
-    else e = prefix_state([&](uint32_t i) { return gload4(reinterpret_cast<const uint8_t *>(A.ptab + i)); },
-                          A.ptab_bits, x, A.hash_mul);
-    if (e == 0u) return;
     int64_t tstart, end;
     int32_t tid;
     locate_text(S, o, tstart, end, tid);
-    if (o + K > end) return;
+    if (o + K > end) return;          // the prefix ran into the next text of a batch
+    auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
+        if (REC) {
+            const int64_t r = j - o - K;
+            if (r < 4) return (rb.x >> (8 * r)) & 0xFFu;
+            if (r < 8) return (rb.y >> (8 * (r - 4))) & 0xFFu;
+        }
+        return gload1(S.text + j);
+    };
     int32_t s = int32_t(e & 0x7fffffffu);
     int64_t d = K;
-    if (e >> 31) emit(A, S, o - tstart, tid, s);
+    if (e >> 31) out(o - tstart, tid, s);
     while (true) {
-        const int32_t t = A.tail[s];
-        if (t >= 0) {
-            if (t != s) {
-                const int32_t p = A.out_pid[A.out_off[t]];
-                const int32_t kb = A.kw_off[p];
-                const int64_t L = A.kw_off[p + 1] - kb;
-                if (o + L > end) return;
-                for (int64_t i = d; i < L; i += 16) {
-                    uint32_t diff = 0;
-#pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        if (i + u < L) diff |= uint32_t(S.text[o + i + u]) ^ uint32_t(A.kw_bytes[kb + i + u]);
-                    if (diff) return;
-                }
-                emit(A, S, o - tstart, tid, t);
+        const int4 ti = A.tailinfo[s];
+        if (ti.x >= 0) {
+            // forced path: bytes d .. d + ti.z of the text against the keyword
+            const int64_t L = d + ti.z;
+            if (o + L > end) return;
+            int64_t i = d;
+            if (REC) {
+                uint32_t diff = 0;
+                for (; i < L && i < K + 8; ++i) diff |= byte_at(o + i) ^ gload1(A.kw_bytes + ti.y + (i - d));
+                if (diff) return;
             }
+            for (; i < L; i += 16) {
+                uint32_t diff = 0;
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (i + u < L) diff |= gload1(S.text + o + i + u) ^ gload1(A.kw_bytes + ti.y + (i + u - d));
+                if (diff) return;
+            }
+            out(o - tstart, tid, ti.x);
             return;
         }
+        if (ti.x == -2) return;        // a leaf: nothing below
         if (o + d >= end) return;
-        const int32_t e2 = step_global(A, cls, s, S.text[o + d]);
+        const int32_t e2 = step_global(A, cls, s, byte_at(o + d));
         if (e2 == 0) return;
         s = e2 & 0x7fffffff;
         ++d;
-        if (e2 < 0) emit(A, S, o - tstart, tid, s);
+        if (e2 < 0) out(o - tstart, tid, s);
     }
+}
+
+// Out-of-line walk for the streaming kernel's cold paths (partial chunks,
+// full hit regions), so that its hot loop keeps every register.
+__device__ __noinline__ void walk_cold(const DevAut &A, const ScanArgs &S, int64_t o, uint32_t e) {
+    walk_rest<false, false>(A, S, A.cls, o, e, make_uint2(0u, 0u), nullptr);
 }
 
 struct FilterLaunch {
@@ -212,6 +297,10 @@ struct FilterLaunch {
     int64_t n_chunks;        // ceil(V / chunk bytes)
     int64_t c_lo, c_hi;      // interior chunks [c_lo, c_hi): whole chunk + 16 B inside the text
     int32_t filter_kind;
+    int32_t hit_cap;         // entries per wave region
+    uint4 *hits;             // [waves * hit_cap]: {chunk step << 12 | position, prefix-table value,
+                             //  the 8 text bytes after the prefix}
+    int32_t *hit_count;      // [waves]
 };
 
 template <int SEGS>
@@ -258,7 +347,7 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
     constexpr uint32_t kmask = K >= 3 ? 0xFFFFFFu : ((1u << (8 * K)) - 1u);
     // byte map: 2^FLOG2 entries; bit map: 2^(FLOG2-2) words of 32 bits
     constexpr int shift = BITMAP ? 32 - (FLOG2 - 2) : 32 - FLOG2;
-    unsigned long long m = 0;
+    uint32_t mseg[SEGS];
 #pragma unroll
     for (int j = 0; j < SEGS; ++j) {
         uint32_t d[5];
@@ -279,19 +368,21 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
             else v = sfilt[p >> shift];
             mj |= v << s;
         }
-        m |= static_cast<unsigned long long>(mj) << (16 * j);
+        mseg[j] = mj;
     }
-    return m;
+    // bit 16 j + s: segment j, byte s
+    const uint32_t lo = SEGS >= 2 ? (mseg[0] | (mseg[1 % SEGS] << 16)) : mseg[0];
+    const uint32_t hi = SEGS >= 4 ? (mseg[2 % SEGS] | (mseg[3 % SEGS] << 16)) : 0u;
+    return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
 template <int K, bool BITMAP, int SEGS, int FLOG2>
 __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
-    __shared__ __align__(16) uint8_t scls[256];
-    constexpr int PT_SLOTS = FLOG2 >= 17 ? 2048 : 512;   // prefix-table slots that fit beside the filter
+    constexpr int PT_SLOTS = FLOG2 >= 17 ? 2048 : 8192;   // prefix-table slots that fit beside the filter
     __shared__ __align__(16) uint32_t sptab[2 * PT_SLOTS];
-    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 9);
+    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
     if (pt_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(A.ptab);
         uint4 *dst = reinterpret_cast<uint4 *>(sptab);
@@ -301,8 +392,6 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[F.filter_kind - 1]);
         uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
         for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
-        if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
-            reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
     }
     __syncthreads();
 
@@ -314,23 +403,81 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     const int64_t w = int64_t(blockIdx.x) * waves_per_block + wave;
     const int64_t nw = int64_t(gridDim.x) * waves_per_block;
     const uint32_t mul = A.hash_mul;
+    uint4 *hits = F.hits + w * F.hit_cap;
+    int hcount = 0;          // hits stored in this wave's region
 
     // Queue entry = (k << 12) | position in chunk, for chunk qbase + k * qstride.
     int64_t qbase = F.c_lo + w, qstride = nw;
+    bool keep_hits = true;   // false: walk hits here (partial chunks, full region)
     int qlen = 0;
-    auto drain = [&](int take) {
-        // lanes [0, take) walk the newest `take` entries
+    auto drain = [&](int take) __attribute__((always_inline)) {
+        // lanes cover the newest `take` entries, kDrain / 64 each
         wave_sync();
-        const uint32_t e = lane < unsigned(take) ? q[qlen - take + int(lane)] : 0u;
+        uint32_t ent[kDrain / kWave];
+        int64_t off[kDrain / kWave];
+        uint32_t x[kDrain / kWave];
+#pragma unroll
+        for (int r = 0; r < kDrain / kWave; ++r) {
+            // lanes past `take` repeat the first entry, so every load below is valid
+            const int i = int(lane) + r * kWave;
+            ent[r] = q[qlen - take + (i < take ? i : 0)];
+            off[r] = (qbase + int64_t(ent[r] >> 12) * qstride) * CH + int64_t(ent[r] & 4095u) - F.mis;
+        }
         wave_sync();
         qlen -= take;
-        if (lane < unsigned(take)) {
-            const int64_t o = (qbase + int64_t(e >> 12) * qstride) * CH + int64_t(e & 4095u) - F.mis;
-            if (pt_lds) walk_candidate<true>(A, S, scls, sptab, o);
-            else walk_candidate<false>(A, S, scls, sptab, o);
+        uint32_t rb0[kDrain / kWave], rb1[kDrain / kWave];
+        if (keep_hits) {
+            // interior chunks: o + 16 <= n, so the aligned 16 bytes from (o & ~3)
+            // lie in the text; they give the prefix and the 8 bytes after it
+            u32x4 win[kDrain / kWave];
+            uint32_t sh[kDrain / kWave];
+#pragma unroll
+            for (int r = 0; r < kDrain / kWave; ++r) {
+                const uintptr_t a = reinterpret_cast<uintptr_t>(S.text + off[r]);
+                sh[r] = uint32_t(a & 3u);
+                const uint8_t *pa = reinterpret_cast<const uint8_t *>(a & ~uintptr_t(3));
+                win[r].x = gload4(pa);
+                win[r].y = gload4(pa + 4);
+                win[r].z = gload4(pa + 8);
+                win[r].w = gload4(pa + 12);
+            }
+#pragma unroll
+            for (int r = 0; r < kDrain / kWave; ++r) {
+                const uint32_t y0 = __builtin_amdgcn_alignbyte(win[r].y, win[r].x, sh[r]);
+                const uint32_t y1 = __builtin_amdgcn_alignbyte(win[r].z, win[r].y, sh[r]);
+                const uint32_t y2 = __builtin_amdgcn_alignbyte(win[r].w, win[r].z, sh[r]);
+                x[r] = K >= 3 ? (y0 & 0xFFFFFFu) : (y0 & ((1u << (8 * K)) - 1u));
+                rb0[r] = __builtin_amdgcn_alignbyte(y1, y0, uint32_t(K));
+                rb1[r] = __builtin_amdgcn_alignbyte(y2, y1, uint32_t(K));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kDrain / kWave; ++r) {
+                x[r] = 0;
+                rb0[r] = rb1[r] = 0;
+                if (int(lane) + r * kWave < take)
+                    for (int j = 0; j < K; ++j) x[r] |= gload1(S.text + off[r] + j) << (8 * j);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kDrain / kWave; ++r) {
+            uint32_t e = 0;
+            if (int(lane) + r * kWave < take) {
+                if (pt_lds) e = prefix_state([&](uint32_t i) { return sptab[i]; }, A.ptab_bits, x[r], mul);
+                else e = prefix_state([&](uint32_t i) { return gload4(reinterpret_cast<const uint8_t *>(A.ptab + i)); },
+                                      A.ptab_bits, x[r], mul);
+            }
+            const unsigned long long hit = __ballot(e != 0u);
+            if (hit == 0) continue;
+            const int slot = hcount + int(rank_in(hit));
+            if (e != 0u) {
+                if (keep_hits && slot < F.hit_cap) gstore16(hits + slot, ent[r], e, rb0[r], rb1[r]);
+                else walk_cold(A, S, off[r], e);
+            }
+            hcount = imin(hcount + __popcll(hit), F.hit_cap);
         }
     };
-    auto push = [&](unsigned long long m, uint32_t k) {
+    auto push = [&](unsigned long long m, uint32_t k) __attribute__((always_inline)) {
         while (true) {
             const unsigned long long act = __ballot(m != 0);
             if (act == 0) break;
@@ -340,7 +487,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
                 m &= m - 1;
             }
             qlen += __popcll(act);
-            while (qlen >= kWave) drain(kWave);
+            if (qlen >= kDrain) drain(kDrain);
         }
     };
 
@@ -362,12 +509,15 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
             push(filter_chunk<K, BITMAP, SEGS, FLOG2>(rb, lane, sfilt, mul), k++);
             c = c2;
         }
-        if (qlen > 0) drain(qlen);
+        while (qlen > 0) drain(imin(qlen, kDrain));
     }
+    if (lane == 0) F.hit_count[w] = hcount;
 
-    // chunks overlapping an end of the text: [0, p0) and [p1, n_chunks)
-    const int64_t p0 = min(F.c_lo, F.n_chunks);
-    const int64_t p1 = max(F.c_hi, F.c_lo);
+    // chunks overlapping an end of the text: [0, p0) and [p1, n_chunks); their
+    // hits are walked here
+    keep_hits = false;
+    const int64_t p0 = lmin(F.c_lo, F.n_chunks);
+    const int64_t p1 = lmax(F.c_hi, F.c_lo);
     const int64_t n_partial = p0 + (F.n_chunks - p1);
     for (int64_t i = w; i < n_partial; i += nw) {
         const int64_t pc = i < p0 ? i : p1 + (i - p0);
@@ -382,8 +532,41 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         qbase = pc;
         qstride = 0;
         push(m, 0);
-        if (qlen > 0) drain(qlen);
+        while (qlen > 0) drain(imin(qlen, kDrain));
     }
+}
+
+// Second kernel of the filtered policy: one wave per hit region of the
+// streaming kernel walks that region's hits (decoding each offset from the
+// streaming launch's chunk order) and emits the matches.
+struct WalkLaunch {
+    const uint4 *hits;
+    const int32_t *hit_count;
+    int32_t hit_cap;
+    int64_t regions;        // streaming waves
+    int64_t c_lo, nw;       // first interior chunk, streaming waves (chunk stride)
+    int64_t chunk_bytes, mis;
+};
+
+// One block per hit region; its threads share the region's hits and stage
+// the matches they find in LDS.
+__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const DevAut A, const ScanArgs S, const WalkLaunch W) {
+    __shared__ __align__(16) uint8_t scls[256];
+    __shared__ MatchStage st;
+    if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
+        reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
+    if (threadIdx.x == 0) st.n = 0;
+    __syncthreads();
+    const int64_t region = blockIdx.x;
+    const int32_t cnt = W.hit_count[region];
+    const uint4 *h = W.hits + region * W.hit_cap;
+    for (int32_t i = int32_t(threadIdx.x); i < cnt; i += int32_t(blockDim.x)) {
+        const uint4 rec = h[i];
+        const int64_t chunk = W.c_lo + region + int64_t(rec.x >> 12) * W.nw;
+        const int64_t o = chunk * W.chunk_bytes + int64_t(rec.x & 4095u) - W.mis;
+        walk_rest<true, true>(A, S, scls, o, rec.y, make_uint2(rec.z, rec.w), &st);
+    }
+    flush_stage(S, &st);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,8 +590,8 @@ __global__ __launch_bounds__(1024) void direct_kernel(const DevAut A, const Scan
         for (int i = threadIdx.x; i < L.table_bytes / 16; i += blockDim.x) dst[i] = src[i];
     }
     const int64_t t0 = int64_t(blockIdx.x) * L.tile;
-    const int64_t t1 = min(t0 + L.tile, S.n);
-    const int64_t h1 = min(t1 + L.halo, S.n);
+    const int64_t t1 = lmin(t0 + L.tile, S.n);
+    const int64_t h1 = lmin(t1 + L.halo, S.n);
     for (int64_t i = threadIdx.x; i < h1 - t0; i += blockDim.x) stext[i] = S.text[t0 + i];
     __syncthreads();
     for (int64_t o = t0 + threadIdx.x; o < t1; o += blockDim.x) {
@@ -472,8 +655,35 @@ FilteredFn pick_filtered(int K, int kind, int segs) {
 }
 
 int64_t filtered_lds(const FilterGeom &g) {
-    const int64_t pt_slots = g.bytes > (64 << 10) ? 2048 : 512;
-    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + 256 + pt_slots * 8;
+    const int64_t pt_slots = g.bytes > (64 << 10) ? 2048 : 8192;
+    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + pt_slots * 8;
+}
+
+// Launch geometry of the filtered policy for a text of n bytes at `addr`.
+struct FilteredGeom {
+    FilterLaunch F;
+    int64_t grid, waves;
+};
+
+FilteredGeom filtered_geom(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg) {
+    FilteredGeom G{};
+    FilterLaunch &F = G.F;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(text);
+    F.base = reinterpret_cast<const uint8_t *>(addr & ~uintptr_t(15));
+    F.mis = int64_t(addr & 15);
+    F.V = F.mis + n;
+    const int64_t CH = int64_t(cfg.segs) * kSegBytes;
+    F.n_chunks = (F.V + CH - 1) / CH;
+    F.c_lo = F.mis > 0 ? 1 : 0;
+    F.c_hi = F.V >= 16 ? (F.V - 16) / CH : 0;
+    F.filter_kind = cfg.filter;
+    const int waves = cfg.block / kWave;
+    const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
+    const int64_t want = (std::max<int64_t>(interior, 1) + waves - 1) / waves;
+    const int64_t cap = int64_t(a->cu_count) * cfg.grid_per_cu;
+    G.grid = std::max<int64_t>(1, std::min(want, cap));
+    G.waves = G.grid * waves;
+    return G;
 }
 
 std::mutex g_attr_mu;
@@ -541,32 +751,43 @@ int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts, h
     return AC_OK;
 }
 
-int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, hipStream_t stream,
-                std::string &err) {
+int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg) {
+    if (cfg.policy != AC_POLICY_FILTERED || n <= 0) return 0;
+    return filtered_geom(a, text, n, cfg).waves;
+}
+
+int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, const HitScratch &hs,
+                hipStream_t stream, std::string &err) {
     if (S.n <= 0) return AC_OK;
     const Plan &P = a->host;
     hipError_t e = hipSuccess;
     if (cfg.policy == AC_POLICY_FILTERED) {
-        const FilterGeom g = filter_geom(cfg.filter);
-        FilterLaunch F;
-        const uintptr_t addr = reinterpret_cast<uintptr_t>(S.text);
-        F.base = reinterpret_cast<const uint8_t *>(addr & ~uintptr_t(15));
-        F.mis = int64_t(addr & 15);
-        F.V = F.mis + S.n;
-        const int64_t CH = int64_t(cfg.segs) * kSegBytes;
-        F.n_chunks = (F.V + CH - 1) / CH;
-        F.c_lo = F.mis > 0 ? 1 : 0;
-        F.c_hi = F.V >= 16 ? (F.V - 16) / CH : 0;
-        F.filter_kind = g.kind;
-        const int waves = cfg.block / kWave;
+        FilteredGeom G = filtered_geom(a, S.text, S.n, cfg);
+        FilterLaunch &F = G.F;
+        if (!hs.hits || !hs.count || hs.regions < G.waves || hs.cap <= 0) {
+            err = "scan scratch too small for the launch";
+            return AC_EINVAL;
+        }
+        F.hits = hs.hits;
+        F.hit_count = hs.count;
+        F.hit_cap = hs.cap;
         const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
-        const int64_t want = (std::max<int64_t>(interior, 1) + waves - 1) / waves;
-        const int64_t cap = int64_t(a->cu_count) * cfg.grid_per_cu;
-        const int64_t grid = std::max<int64_t>(1, std::min(want, cap));
         // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
-        if (interior / (grid * waves) >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
+        if (interior / G.waves >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
         FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs);
-        hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
+        hipLaunchKernelGGL(fn, dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
+        e = hipGetLastError();
+        if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
+        WalkLaunch W;
+        W.hits = hs.hits;
+        W.hit_count = hs.count;
+        W.hit_cap = hs.cap;
+        W.regions = G.waves;
+        W.c_lo = F.c_lo;
+        W.nw = G.waves;
+        W.chunk_bytes = int64_t(cfg.segs) * kSegBytes;
+        W.mis = F.mis;
+        hipLaunchKernelGGL(walk_kernel, dim3(unsigned(G.waves)), dim3(kWalkBlock), 0, stream, a->dev, S, W);
         e = hipGetLastError();
     } else if (cfg.policy == AC_POLICY_DIRECT) {
         if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }

@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "pfac.h"
 
 namespace pfac {
@@ -59,6 +61,7 @@ struct Plan {
     int32_t ptab_bits = 0;
     std::vector<uint32_t> ptab;    // [2 << ptab_bits]: {prefix | valid, state | final}
     std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1
+    std::vector<int32_t> tailinfo; // [4 S]: {leaf or -1, kw_bytes position, remaining bytes, 0}
     std::vector<uint8_t> kw_bytes; // keywords back to back
     std::vector<int32_t> kw_off;   // [n + 1]
     double build_ms = 0.0;
@@ -75,6 +78,7 @@ struct DevAut {
     const int32_t *out_pid;
     const uint32_t *ptab;          // exact prefix table (global copy)
     const int32_t *tail;
+    const int4 *tailinfo;
     const uint8_t *kw_bytes;
     const int32_t *kw_off;
     int32_t C, S, S_dense, K, max_len;
@@ -118,8 +122,18 @@ namespace pfac {
 int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
                  const ac_build_opts *opts, Plan &out, std::string &err);
 uint32_t prefix_hash(uint32_t x, uint32_t mul);
+// Per-stream scratch of the filtered policy: one hit region per streaming wave.
+struct HitScratch {
+    uint4 *hits = nullptr;         // [regions * cap]
+    int32_t *count = nullptr;      // [regions]
+    int64_t regions = 0;
+    int32_t cap = 0;
+};
+constexpr int32_t kHitCap = 1024;
+
 // kernels.hip
-int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg,
+int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
+int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg, const HitScratch &hs,
                 hipStream_t stream, std::string &err);
 int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
                 hipStream_t stream, std::string &err);

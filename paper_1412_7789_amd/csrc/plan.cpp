@@ -264,6 +264,19 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             else if (!is_final(c)) P.tail[size_t(s)] = P.tail[size_t(c)];
         }
     }
+    // per state: {leaf, position in kw_bytes of the first byte below s, bytes
+    // from s down to the leaf, 0} when tail[s] is a deeper leaf; first field
+    // -2 when s is itself a leaf, -1 when the path below s is not forced
+    P.tailinfo.assign(size_t(S) * 4, 0);
+    for (int32_t s = 0; s < S; ++s) {
+        const int32_t t = P.tail[size_t(s)];
+        int32_t *ti = &P.tailinfo[size_t(s) * 4];
+        if (t < 0 || t == s) { ti[0] = t < 0 ? -1 : -2; continue; }
+        const int32_t p = P.out_pid[size_t(P.out_off[size_t(t)])];
+        ti[0] = t;
+        ti[1] = int32_t(offsets[p] - offsets[0]) + P.depth[size_t(s)];
+        ti[2] = P.depth[size_t(t)] - P.depth[size_t(s)];
+    }
     // keyword bytes (for tail comparisons) with int32 offsets
     P.kw_bytes.assign(bytes + offsets[0], bytes + offsets[0] + total);
     P.kw_off.resize(size_t(n) + 1);
