@@ -103,7 +103,12 @@ typedef struct {
     int32_t grid_per_cu;    /* resident blocks per compute unit; 0 = auto        */
     int32_t table_in_lds;   /* DIRECT: -1/0 = auto, 1 = force LDS, 2 = global     */
     int32_t flags;          /* AC_LAUNCH_* bits                                   */
-    int32_t reserved[5];
+    int32_t stride;         /* FILTERED: 1 = test every offset's prefix; 2 = test
+                             * odd offsets against the keywords' 3-byte windows at
+                             * positions 0 and 1 (needs every keyword >= 4 bytes),
+                             * each positive test making both offsets of its pair
+                             * candidates; 0 = auto                              */
+    int32_t reserved[4];
 } ac_launch;
 
 /* Record HIP events on the call's stream immediately before and after the
@@ -177,7 +182,7 @@ typedef struct {
     int32_t n_dense_states;  /* states [0, n_dense_states) have dense rows      */
     int32_t dense_depth;     /* every state of depth <= dense_depth is dense    */
     int32_t n_prefixes;      /* distinct keyword prefixes of prefix_len bytes   */
-    int32_t reserved0;
+    int32_t n_windows2;      /* distinct 3-byte windows at positions 0 and 1 (0 = stride 2 unavailable) */
     int64_t dense_bytes, compact_bytes, output_bytes, filter_bytes, device_bytes;
     double build_ms;         /* host build + upload time                        */
     int64_t prefix_table_bytes;  /* exact prefix -> state table                 */
@@ -221,7 +226,8 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *   AC_TABLE_DEPTH      int32[S]           trie depth of each state
  *   AC_TABLE_PREFIX     uint32[2*slots]    {prefix | 1<<31, state | final bit}, 0 = empty
  *   AC_TABLE_TAIL       int32[S]           leaf reached by a forced path, or -1
- *   AC_TABLE_FILTER_*   filter maps (AC_FILTER_* + 100)
+ *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
+ *                              k = 4 + AC_FILTER_* (stride 2, may be empty)
  */
 #define AC_TABLE_CLASS_MAP  1
 #define AC_TABLE_DENSE      2

@@ -42,7 +42,7 @@ class BatchMatches(ctypes.Structure):
 class Launch(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("filter", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("segs", ctypes.c_int32), ("grid_per_cu", ctypes.c_int32), ("table_in_lds", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("flags", ctypes.c_int32), ("stride", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
     _fields_ = [("n_patterns", ctypes.c_int32), ("n_states", ctypes.c_int32), ("n_classes", ctypes.c_int32),
                 ("min_len", ctypes.c_int32), ("max_len", ctypes.c_int32), ("prefix_len", ctypes.c_int32),
                 ("n_dense_states", ctypes.c_int32), ("dense_depth", ctypes.c_int32),
-                ("n_prefixes", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n_prefixes", ctypes.c_int32), ("n_windows2", ctypes.c_int32),
                 ("dense_bytes", ctypes.c_int64), ("compact_bytes", ctypes.c_int64),
                 ("output_bytes", ctypes.c_int64), ("filter_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),

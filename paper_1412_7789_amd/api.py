@@ -30,10 +30,10 @@ def _csr(keywords: Sequence[bytes]) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def launch_config(policy: int = 0, filter: int = 0, block: int = 0, segs: int = 0,
-                  grid_per_cu: int = 0, table_in_lds: int = 0, flags: int = 0) -> L.Launch:
+                  grid_per_cu: int = 0, table_in_lds: int = 0, flags: int = 0, stride: int = 0) -> L.Launch:
     cfg = L.Launch()
     cfg.policy, cfg.filter, cfg.block, cfg.segs = policy, filter, block, segs
-    cfg.grid_per_cu, cfg.table_in_lds, cfg.flags = grid_per_cu, table_in_lds, flags
+    cfg.grid_per_cu, cfg.table_in_lds, cfg.flags, cfg.stride = grid_per_cu, table_in_lds, flags, stride
     return cfg
 
 

@@ -38,7 +38,8 @@ namespace {
 
 constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
 constexpr int kDrain = 192;      // candidates taken per drain (3 per lane)
-constexpr int kWalkBlock = 512;  // threads of the walk kernel per hit region
+constexpr int kWalkBlock = 1024;   // threads of a walk-kernel block
+constexpr int kWalkRegions = 16;   // hit regions per walk-kernel block
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
@@ -112,7 +113,7 @@ __device__ void emit(const DevAut &A, const ScanArgs &S, int64_t off, int32_t ti
 // Block-level staging of matches in LDS: one global atomic per block instead
 // of one per match.  Matches beyond the stage's capacity go straight out
 // through emit().
-constexpr int kStageCap = 1024;
+constexpr int kStageCap = 4096;
 struct MatchStage {
     int64_t off[kStageCap];
     int32_t pid[kStageCap];
@@ -184,18 +185,21 @@ __device__ __forceinline__ uint32_t hash24(uint32_t x, uint32_t mul) {
     return static_cast<uint32_t>(__umul24(x, mul));
 }
 
-// Exact prefix lookup: {state at depth K | final bit} for the K-byte prefix x,
-// or 0 when no keyword starts with x.  The table is at most half full, so the
-// linear probe always meets an empty slot.
+// Exact prefix lookup for the K-byte prefix x: returns {key, value} of its
+// slot -- key = x | next byte << 24, value = state at depth K | has-next bit
+// 30 | final bit 31 -- or value 0 when no keyword starts with x.  The table
+// is at most half full, so the linear probe always meets an empty slot.
+constexpr uint32_t kHasNext = 0x40000000u;
+constexpr uint32_t kStateMask = 0x3fffffffu;
+
 template <typename Load>
-__device__ __forceinline__ uint32_t prefix_state(Load load, int bits, uint32_t x, uint32_t mul) {
+__device__ __forceinline__ uint2 prefix_state(Load load, int bits, uint32_t x, uint32_t mul) {
     const uint32_t mask = (1u << bits) - 1u;
-    const uint32_t key = x | 0x80000000u;
     uint32_t slot = (hash24(x, mul) >> (32 - bits)) & mask;
     while (true) {
-        const uint32_t k = load(2 * slot);
-        if (k == key) return load(2 * slot + 1);
-        if (k == 0u) return 0u;
+        const uint2 kv = load(slot);
+        if (kv.y == 0u) return kv;
+        if ((kv.x & 0xFFFFFFu) == x) return kv;
         slot = (slot + 1u) & mask;
     }
 }
@@ -249,7 +253,7 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
         }
         return gload1(S.text + j);
     };
-    int32_t s = int32_t(e & 0x7fffffffu);
+    int32_t s = int32_t(e & kStateMask);
     int64_t d = K;
     if (e >> 31) out(o - tstart, tid, s);
     while (true) {
@@ -340,8 +344,9 @@ __device__ __noinline__ void load_partial(const FilterLaunch &F, int64_t c, unsi
 }
 
 // Candidate mask of one chunk: bit 16 j + s is set when the K bytes at offset
-// s of the lane's 16 bytes in segment j hash to a set filter entry.
-template <int K, bool BITMAP, int SEGS, int FLOG2>
+// s of the lane's 16 bytes in segment j hash to a set filter entry (stride
+// 1), or when the 3 bytes at the odd offset of s's pair do (stride 2).
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE>
 __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
                                                            const uint8_t *sfilt, uint32_t mul) {
     constexpr uint32_t kmask = K >= 3 ? 0xFFFFFFu : ((1u << (8 * K)) - 1u);
@@ -358,7 +363,7 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
         d[4] = lane == 63 ? from_next_seg : from_next_lane;
         uint32_t mj = 0;
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
+        for (int s = STRIDE - 1; s < 16; s += STRIDE) {
             const int w = s >> 2, r = s & 3;
             uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
             if (K < 3) x &= kmask;
@@ -368,6 +373,8 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
             else v = sfilt[p >> shift];
             mj |= v << s;
         }
+        // stride 2: a window tested at odd s covers the offset pair (s - 1, s)
+        if (STRIDE == 2) mj |= mj >> 1;
         mseg[j] = mj;
     }
     // bit 16 j + s: segment j, byte s
@@ -376,7 +383,7 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
-template <int K, bool BITMAP, int SEGS, int FLOG2>
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE>
 __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         for (int i = threadIdx.x; i < (2 << A.ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
     }
     {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[F.filter_kind - 1]);
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[(STRIDE - 1) * kNumFilterKinds + F.filter_kind - 1]);
         uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
         for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
     }
@@ -463,9 +470,18 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         for (int r = 0; r < kDrain / kWave; ++r) {
             uint32_t e = 0;
             if (int(lane) + r * kWave < take) {
-                if (pt_lds) e = prefix_state([&](uint32_t i) { return sptab[i]; }, A.ptab_bits, x[r], mul);
-                else e = prefix_state([&](uint32_t i) { return gload4(reinterpret_cast<const uint8_t *>(A.ptab + i)); },
-                                      A.ptab_bits, x[r], mul);
+                uint2 kv;
+                if (pt_lds) kv = prefix_state([&](uint32_t i) { return make_uint2(sptab[2 * i], sptab[2 * i + 1]); },
+                                              A.ptab_bits, x[r], mul);
+                else kv = prefix_state([&](uint32_t i) {
+                              return make_uint2(gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i)),
+                                                gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i + 1)));
+                          }, A.ptab_bits, x[r], mul);
+                e = kv.y;
+                // a non-final prefix state whose only child's byte differs from
+                // the text's next byte ends the walk here (interior chunks only:
+                // there rb0 holds that byte)
+                if (keep_hits && (e & kHasNext) && !(e >> 31) && (kv.x >> 24) != (rb0[r] & 0xFFu)) e = 0u;
             }
             const unsigned long long hit = __ballot(e != 0u);
             if (hit == 0) continue;
@@ -501,12 +517,12 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         while (c < F.c_hi) {
             const int64_t c1 = c + nw;
             if (c1 < F.c_hi) load_interior<SEGS>(F, c1, lane, rb);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2>(ra, lane, sfilt, mul), k++);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(ra, lane, sfilt, mul), k++);
             c = c1;
             if (c >= F.c_hi) break;
             const int64_t c2 = c + nw;
             if (c2 < F.c_hi) load_interior<SEGS>(F, c2, lane, ra);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2>(rb, lane, sfilt, mul), k++);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(rb, lane, sfilt, mul), k++);
             c = c2;
         }
         while (qlen > 0) drain(imin(qlen, kDrain));
@@ -523,7 +539,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         const int64_t pc = i < p0 ? i : p1 + (i - p0);
         ChunkRegs<SEGS> r;
         load_partial<SEGS>(F, pc, lane, r);
-        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2>(r, lane, sfilt, mul);
+        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(r, lane, sfilt, mul);
         for (int b = 0; b < SEGS * 16; ++b) {
             // keep offsets o with 0 <= o and o + K <= n
             const int64_t o = pc * CH + (b >> 4) * kSegBytes + int64_t(lane) * 16 + (b & 15) - F.mis;
@@ -548,20 +564,32 @@ struct WalkLaunch {
     int64_t chunk_bytes, mis;
 };
 
-// One block per hit region; its threads share the region's hits and stage
-// the matches they find in LDS.
+// Each block takes kWalkRegions consecutive hit regions and spreads their
+// hits over all its threads (one flat index over the regions' counts); the
+// matches found are staged in LDS and leave with one global atomic.
 __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const DevAut A, const ScanArgs S, const WalkLaunch W) {
     __shared__ __align__(16) uint8_t scls[256];
     __shared__ MatchStage st;
+    __shared__ int32_t first[kWalkRegions + 1];   // prefix sums of the regions' hit counts
+    const int64_t r0 = int64_t(blockIdx.x) * kWalkRegions;
+    const int nr = int(lmin(kWalkRegions, W.regions - r0));
     if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
         reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
-    if (threadIdx.x == 0) st.n = 0;
+    if (threadIdx.x < kWalkRegions) first[threadIdx.x + 1] = int(threadIdx.x) < nr ? W.hit_count[r0 + threadIdx.x] : 0;
+    if (threadIdx.x == 0) {
+        st.n = 0;
+        first[0] = 0;
+    }
     __syncthreads();
-    const int64_t region = blockIdx.x;
-    const int32_t cnt = W.hit_count[region];
-    const uint4 *h = W.hits + region * W.hit_cap;
-    for (int32_t i = int32_t(threadIdx.x); i < cnt; i += int32_t(blockDim.x)) {
-        const uint4 rec = h[i];
+    if (threadIdx.x == 0)
+        for (int j = 0; j < kWalkRegions; ++j) first[j + 1] += first[j];
+    __syncthreads();
+    const int32_t total = first[kWalkRegions];
+    for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
+        int j = 0;
+        while (first[j + 1] <= i) ++j;          // region of flat index i
+        const int64_t region = r0 + j;
+        const uint4 rec = W.hits[region * W.hit_cap + (i - first[j])];
         const int64_t chunk = W.c_lo + region + int64_t(rec.x >> 12) * W.nw;
         const int64_t o = chunk * W.chunk_bytes + int64_t(rec.x & 4095u) - W.mis;
         walk_rest<true, true>(A, S, scls, o, rec.y, make_uint2(rec.z, rec.w), &st);
@@ -629,29 +657,31 @@ __global__ __launch_bounds__(256) void probe_read_kernel(const uint8_t *buf, int
 
 using FilteredFn = void (*)(const DevAut, const ScanArgs, const FilterLaunch);
 
-template <int K, bool BM, int FLOG2>
+template <int K, bool BM, int FLOG2, int STRIDE>
 FilteredFn pick_segs(int segs) {
     switch (segs) {
-        case 1: return filtered_kernel<K, BM, 1, FLOG2>;
-        case 2: return filtered_kernel<K, BM, 2, FLOG2>;
-        default: return filtered_kernel<K, BM, 4, FLOG2>;
+        case 1: return filtered_kernel<K, BM, 1, FLOG2, STRIDE>;
+        case 2: return filtered_kernel<K, BM, 2, FLOG2, STRIDE>;
+        default: return filtered_kernel<K, BM, 4, FLOG2, STRIDE>;
     }
 }
 
-template <int K>
+template <int K, int STRIDE>
 FilteredFn pick_filter(int kind, int segs) {
     switch (kind) {
-        case AC_FILTER_BYTES17: return pick_segs<K, false, 17>(segs);
-        case AC_FILTER_BITS20: return pick_segs<K, true, 17>(segs);
-        case AC_FILTER_BYTES16: return pick_segs<K, false, 16>(segs);
-        default: return pick_segs<K, true, 16>(segs);
+        case AC_FILTER_BYTES17: return pick_segs<K, false, 17, STRIDE>(segs);
+        case AC_FILTER_BITS20: return pick_segs<K, true, 17, STRIDE>(segs);
+        case AC_FILTER_BYTES16: return pick_segs<K, false, 16, STRIDE>(segs);
+        default: return pick_segs<K, true, 16, STRIDE>(segs);
     }
 }
 
-FilteredFn pick_filtered(int K, int kind, int segs) {
-    if (K == 1) return pick_filter<1>(kind, segs);
-    if (K == 2) return pick_filter<2>(kind, segs);
-    return pick_filter<3>(kind, segs);
+// stride 2 exists for K = 3 only
+FilteredFn pick_filtered(int K, int kind, int segs, int stride) {
+    if (stride == 2) return pick_filter<3, 2>(kind, segs);
+    if (K == 1) return pick_filter<1, 1>(kind, segs);
+    if (K == 2) return pick_filter<2, 1>(kind, segs);
+    return pick_filter<3, 1>(kind, segs);
 }
 
 int64_t filtered_lds(const FilterGeom &g) {
@@ -701,9 +731,18 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
     if (cfg.policy == AC_POLICY_AUTO) cfg.policy = AC_POLICY_FILTERED;
     if (batch) cfg.policy = AC_POLICY_FILTERED;
     if (cfg.policy == AC_POLICY_FILTERED) {
+        // Stride 2 halves the filter work but doubles the keys in the filter;
+        // it pays while the 2^20-bit map stays sparse (measured on MI355X:
+        // 1000 printable keywords 0.34 vs 0.40 ms per GiB; 20000 byte
+        // keywords 0.78 vs 0.68 ms).
+        const bool sampled_ok = P.sampled && P.n_windows2 <= 8192;
+        if (cfg.stride != 1 && cfg.stride != 2) cfg.stride = sampled_ok ? 2 : 1;
+        if (cfg.stride == 2 && !P.sampled) cfg.stride = 1;
         if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_BITS19) {
+            // keys in the filter: prefixes (stride 1) or windows (stride 2)
+            const int64_t keys = cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;
             const bool small_text = len < (int64_t(16) << 20);
-            const bool many = P.n_prefixes > 1500;
+            const bool many = keys > 1500;
             if (small_text) cfg.filter = many ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;
             else cfg.filter = many ? AC_FILTER_BITS20 : AC_FILTER_BYTES17;
         }
@@ -715,8 +754,8 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
             g = filter_geom(cfg.filter);
         }
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
-        // the bit maps need more registers: two segments keep them spill-free
-        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = g.bitmap ? 2 : 4;
+        // at stride 1 the bit maps need two segments to stay spill-free
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = (g.bitmap && cfg.stride == 1) ? 2 : 4;
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
     } else {
@@ -774,7 +813,7 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
         // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
         if (interior / G.waves >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
-        FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs);
+        FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs, cfg.stride);
         hipLaunchKernelGGL(fn, dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
         e = hipGetLastError();
         if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
@@ -787,7 +826,8 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         W.nw = G.waves;
         W.chunk_bytes = int64_t(cfg.segs) * kSegBytes;
         W.mis = F.mis;
-        hipLaunchKernelGGL(walk_kernel, dim3(unsigned(G.waves)), dim3(kWalkBlock), 0, stream, a->dev, S, W);
+        const int64_t wblocks = (G.waves + kWalkRegions - 1) / kWalkRegions;
+        hipLaunchKernelGGL(walk_kernel, dim3(unsigned(wblocks)), dim3(kWalkBlock), 0, stream, a->dev, S, W);
         e = hipGetLastError();
     } else if (cfg.policy == AC_POLICY_DIRECT) {
         if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }

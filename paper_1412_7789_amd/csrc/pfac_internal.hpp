@@ -37,7 +37,11 @@ inline FilterGeom filter_geom(int kind) {
         default: return {0, false, 0, 0, 0};
     }
 }
-constexpr int kNumFilters = 4;
+constexpr int kNumFilterKinds = 4;
+// Filter sets: [0, 4) test every offset against the keywords' K-byte
+// prefixes; [4, 8) test odd offsets against the 3-byte windows at keyword
+// positions 0 and 1 (built when K = 3 and every keyword has >= 4 bytes).
+constexpr int kNumFilters = 2 * kNumFilterKinds;
 
 // Host-side build result (the "plan").  States are numbered breadth first,
 // so the children of a state are contiguous and sorted by byte, and every
@@ -57,7 +61,9 @@ struct Plan {
     std::vector<int32_t> node;     // [2 * (S - S_dense)]
     uint32_t hash_mul = kDefaultHashMul;
     int32_t n_prefixes = 0;
-    std::vector<uint8_t> filter[kNumFilters];   // indexed by kind - 1
+    int32_t n_windows2 = 0;        // distinct 3-byte windows at keyword positions 0 and 1
+    bool sampled = false;          // the stride-2 filters exist
+    std::vector<uint8_t> filter[kNumFilters];   // indexed by (stride - 1) * 4 + kind - 1
     int32_t ptab_bits = 0;
     std::vector<uint32_t> ptab;    // [2 << ptab_bits]: {prefix | valid, state | final}
     std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1

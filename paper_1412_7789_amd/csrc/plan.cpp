@@ -56,7 +56,7 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
         P.min_len = std::min<int64_t>(P.min_len, L);
         P.max_len = std::max<int64_t>(P.max_len, L);
     }
-    if (total >= (int64_t(1) << 31) - 1) { err = "ac_build: more than 2^31 trie states"; return AC_EINVAL; }
+    if (total >= (int64_t(1) << 30) - 1) { err = "ac_build: more than 2^30 trie states"; return AC_EINVAL; }
     P.K = std::min(kMaxPrefix, P.min_len);
 
     // ---- Goto trie, built in lexicographic keyword order -------------------
@@ -207,24 +207,47 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
     std::sort(prefixes.begin(), prefixes.end());
     prefixes.erase(std::unique(prefixes.begin(), prefixes.end()), prefixes.end());
     P.n_prefixes = int32_t(prefixes.size());
-    for (int kind = 1; kind <= kNumFilters; ++kind) {
-        FilterGeom g = filter_geom(kind);
-        std::vector<uint8_t> &f = P.filter[kind - 1];
-        f.assign(size_t(g.bytes), 0);
-        for (uint32_t x : prefixes) {
-            uint32_t h = prefix_hash(x, mul);
-            if (g.bitmap) {
-                uint32_t w = h >> g.shift, bit = h & 31u;
-                f[size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
-            } else {
-                f[size_t(h >> g.shift)] = 1;
+    // windows for the stride-2 filters: bytes [0, 3) and [1, 4) of each keyword
+    std::vector<uint32_t> windows;
+    P.sampled = P.K == 3 && P.min_len >= 4;
+    if (P.sampled) {
+        windows.reserve(size_t(n) * 2);
+        for (int32_t p = 0; p < n; ++p) {
+            const uint8_t *k = kw(p);
+            windows.push_back(uint32_t(k[0]) | uint32_t(k[1]) << 8 | uint32_t(k[2]) << 16);
+            windows.push_back(uint32_t(k[1]) | uint32_t(k[2]) << 8 | uint32_t(k[3]) << 16);
+        }
+        std::sort(windows.begin(), windows.end());
+        windows.erase(std::unique(windows.begin(), windows.end()), windows.end());
+    }
+    P.n_windows2 = int32_t(windows.size());
+    for (int set = 0; set < 2; ++set) {
+        const std::vector<uint32_t> &keys = set == 0 ? prefixes : windows;
+        for (int kind = 1; kind <= kNumFilterKinds; ++kind) {
+            FilterGeom g = filter_geom(kind);
+            std::vector<uint8_t> &f = P.filter[set * kNumFilterKinds + kind - 1];
+            if (set == 1 && !P.sampled) { f.clear(); continue; }
+            f.assign(size_t(g.bytes), 0);
+            for (uint32_t x : keys) {
+                uint32_t h = prefix_hash(x, mul);
+                if (g.bitmap) {
+                    uint32_t w = h >> g.shift, bit = h & 31u;
+                    f[size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
+                } else {
+                    f[size_t(h >> g.shift)] = 1;
+                }
             }
         }
     }
+
     // ---- exact prefix table: K-byte prefix -> state at depth K ------------
     // Open addressing with linear probing, at most half full, probed from
-    // the same product as the filters.  Slot = {prefix | valid bit, state |
-    // final bit}; a zero key marks an empty slot.
+    // the same product as the filters.  Slot = {key, value}:
+    //   key   = prefix (24 bits) | next byte << 24
+    //   value = state | has-next << 30 | final << 31, 0 for an empty slot.
+    // When the state has exactly one child, "next byte" is that child's edge
+    // byte and has-next is set: an offset whose following byte differs
+    // cannot match deeper than the prefix.
     {
         int bits = 6;
         while ((int64_t(1) << bits) < 2 * int64_t(P.n_prefixes)) ++bits;
@@ -242,10 +265,15 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
                 s = lo;
             }
             uint32_t slot = prefix_hash(x, mul) >> (32 - bits);
-            while (P.ptab[size_t(slot) * 2] != 0u && P.ptab[size_t(slot) * 2] != (x | 0x80000000u))
+            while (P.ptab[size_t(slot) * 2 + 1] != 0u && (P.ptab[size_t(slot) * 2] & 0xFFFFFFu) != x)
                 slot = (slot + 1u) & mask;
-            P.ptab[size_t(slot) * 2] = x | 0x80000000u;
-            P.ptab[size_t(slot) * 2 + 1] = uint32_t(s) | (is_final(s) ? 0x80000000u : 0u);
+            uint32_t key = x, val = uint32_t(s) | (is_final(s) ? 0x80000000u : 0u);
+            if (P.n_child[size_t(s)] == 1) {
+                key |= uint32_t(P.label[size_t(P.first_child[size_t(s)])]) << 24;
+                val |= 0x40000000u;
+            }
+            P.ptab[size_t(slot) * 2] = key;
+            P.ptab[size_t(slot) * 2 + 1] = val;
         }
     }
 

@@ -157,14 +157,13 @@ def test_prefix_table_and_tails(name, kws):
         return s
 
     def lookup(x):
+        """(key, value) of x's slot; value 0 when absent."""
         bits = int(np.log2(len(T.ptab) // 2))
         slot = T.plan.hash(x) >> (32 - bits)
         while True:
             k, v = int(T.ptab[2 * slot]), int(T.ptab[2 * slot + 1])
-            if k == (x | 0x80000000):
-                return v
-            if k == 0:
-                return 0
+            if v == 0 or (k & 0xFFFFFF) == x:
+                return k, v
             slot = (slot + 1) % (len(T.ptab) // 2)
 
     keyset = set(kws)
@@ -172,16 +171,21 @@ def test_prefix_table_and_tails(name, kws):
     assert T.info["n_prefixes"] == len(pref)
     for pr in pref:
         x = int.from_bytes(pr, "little")
-        v = lookup(x)
+        k, v = lookup(x)
         s = walk(pr)
-        assert v & 0x7FFFFFFF == s
+        assert v & 0x3FFFFFFF == s
         assert bool(v >> 31) == (pr in keyset)
+        ch = T.children(s)
+        # has-next flag and the single child's byte
+        assert bool(v & 0x40000000) == (len(ch) == 1)
+        if len(ch) == 1:
+            assert k >> 24 == [b for b in range(256) if T.step(s, b) is not None][0]
     # values that start no keyword are absent
     rng = np.random.default_rng(1)
     for x in rng.integers(0, 1 << (8 * K), size=2000):
         pr = int(x).to_bytes(K, "little")
         if pr not in pref:
-            assert lookup(int(x)) == 0
+            assert lookup(int(x))[1] == 0
     # tails: tail[s] = leaf reached by a forced path with no keyword ending strictly between
     for s in range(T.S):
         path, t = [s], s

@@ -50,6 +50,9 @@ POLICIES = [
     ("filtered-bytes16-s1", dict(policy=1, filter=3, segs=1)),
     ("filtered-bits19-s4-b256", dict(policy=1, filter=4, segs=4, block=256)),
     ("filtered-bytes17-s2-b512", dict(policy=1, filter=1, segs=2, block=512)),
+    ("stride1-bytes17-s4", dict(policy=1, filter=1, segs=4, stride=1)),
+    ("stride2-bits20-s4", dict(policy=1, filter=2, segs=4, stride=2)),
+    ("stride2-bytes16-s1-b256", dict(policy=1, filter=3, segs=1, stride=2, block=256)),
     ("direct-lds", dict(policy=2, table_in_lds=1)),
     ("direct-global", dict(policy=2, table_in_lds=2)),
 ]
@@ -127,8 +130,8 @@ def test_plants_straddling_chunk_boundaries():
                     t[o:o + len(k)] = np.frombuffer(k, dtype=np.uint8)
                     texts.append(t)
     a = pf.Automaton(kws)
-    for segs in (1, 2, 4):
-        cfg = pf.launch_config(policy=1, segs=segs)
+    for segs, stride in ((1, 1), (2, 2), (4, 1), (4, 2)):
+        cfg = pf.launch_config(policy=1, segs=segs, stride=stride)
         for i, t in enumerate(texts):
             if i % 16 == 0:
                 say("straddle", segs, i)
