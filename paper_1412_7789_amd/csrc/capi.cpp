@@ -45,11 +45,14 @@ int ensure_hits(CountSlot &s, int64_t regions) {
     if (s.hs.regions >= regions) return AC_OK;
     if (s.hs.hits) (void)hipFree(s.hs.hits);
     if (s.hs.count) (void)hipFree(s.hs.count);
+    if (s.hs.kmin) (void)hipFree(s.hs.kmin);
     s.hs = HitScratch();
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.hs.hits), size_t(regions) * kHitCap * sizeof(uint4));
     if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit regions): ") + hipGetErrorString(e));
     e = hipMalloc(reinterpret_cast<void **>(&s.hs.count), size_t(regions) * sizeof(int32_t));
     if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit counts): ") + hipGetErrorString(e));
+    e = hipMalloc(reinterpret_cast<void **>(&s.hs.kmin), size_t(regions) * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit steps): ") + hipGetErrorString(e));
     s.hs.regions = regions;
     s.hs.cap = kHitCap;
     return AC_OK;

@@ -43,6 +43,15 @@ constexpr int kWalkRegions = 16;   // hit regions per walk-kernel block
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
+
+// Minimum of v over the wave's lanes.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = uint32_t(__shfl_xor(int(v), d));
+        v = o < v ? o : v;
+    }
+    return v;
+}
 __device__ __forceinline__ int64_t lmin(int64_t a, int64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t lmax(int64_t a, int64_t b) { return a > b ? a : b; }
 
@@ -91,7 +100,7 @@ __device__ __forceinline__ void wave_sync() {
 // Reports every keyword id of final state s at `off` (relative to its text).
 // Called from divergent code: the lanes calling it together share one atomic
 // per round; lanes with more ids loop more rounds.
-__device__ void emit(const DevAut &A, const ScanArgs &S, int64_t off, int32_t tid, int32_t s) {
+__device__ __forceinline__ void emit(const DevAut &A, const ScanArgs &S, int64_t off, int32_t tid, int32_t s) {
     const int32_t k0 = A.out_off[s], k1 = A.out_off[s + 1];
     for (int32_t k = k0; k < k1; ++k) {
         const unsigned long long act = __ballot(1);
@@ -288,12 +297,6 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
     }
 }
 
-// Out-of-line walk for the streaming kernel's cold paths (partial chunks,
-// full hit regions), so that its hot loop keeps every register.
-__device__ __noinline__ void walk_cold(const DevAut &A, const ScanArgs &S, int64_t o, uint32_t e) {
-    walk_rest<false, false>(A, S, A.cls, o, e, make_uint2(0u, 0u), nullptr);
-}
-
 struct FilterLaunch {
     const uint8_t *base;     // text pointer rounded down to 16 bytes
     int64_t mis;             // text - base
@@ -305,6 +308,7 @@ struct FilterLaunch {
     uint4 *hits;             // [waves * hit_cap]: {chunk step << 12 | position, prefix-table value,
                              //  the 8 text bytes after the prefix}
     int32_t *hit_count;      // [waves]
+    uint32_t *hit_kmin;      // [waves]: first chunk step whose hits were not all stored
 };
 
 template <int SEGS>
@@ -328,7 +332,7 @@ __device__ __forceinline__ void load_interior(const FilterLaunch &F, int64_t c, 
 
 // Chunk that overlaps either end of the text: bytes outside it read as 0.
 template <int SEGS>
-__device__ __noinline__ void load_partial(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
+__device__ __forceinline__ void load_partial(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
     auto get4 = [&](int64_t p) {
         uint32_t v = 0;
@@ -383,6 +387,16 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// Streaming kernel of the filtered policy.  Candidate offsets wait in a
+// per-wave LDS queue; a drain takes kDrain of them at once (each lane loads
+// the prefix window of kDrain / 64 candidates with independent loads, then
+// probes the exact prefix table) and appends the surviving prefixes, with the
+// 8 text bytes after them, to the wave's hit region with plain stores.  The
+// streaming loop has no walk, atomic, call or other dependent global access;
+// walk_kernel finishes the stored hits.  Hits that do not fit the region are
+// not stored: the region records the first chunk step that lost one, and a
+// post-pass after the loop re-filters the wave's chunks from that step on
+// (and the partial chunks at the text's ends) and walks their hits itself.
 template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE>
 __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
@@ -403,6 +417,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     __syncthreads();
 
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
+    constexpr int PER_LANE = kDrain / kWave;
     const unsigned lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const int waves_per_block = int(blockDim.x) / kWave;
@@ -411,89 +426,98 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     const int64_t nw = int64_t(gridDim.x) * waves_per_block;
     const uint32_t mul = A.hash_mul;
     uint4 *hits = F.hits + w * F.hit_cap;
-    int hcount = 0;          // hits stored in this wave's region
+    int hcount = 0;                    // hits stored in this wave's region
+    uint32_t kmin = 0xFFFFFFFFu;       // first chunk step that lost a hit
 
     // Queue entry = (k << 12) | position in chunk, for chunk qbase + k * qstride.
     int64_t qbase = F.c_lo + w, qstride = nw;
-    bool keep_hits = true;   // false: walk hits here (partial chunks, full region)
     int qlen = 0;
-    auto drain = [&](int take) __attribute__((always_inline)) {
-        // lanes cover the newest `take` entries, kDrain / 64 each
+
+    auto probe = [&](uint32_t x) __attribute__((always_inline)) -> uint2 {
+        if (pt_lds) return prefix_state([&](uint32_t i) { return make_uint2(sptab[2 * i], sptab[2 * i + 1]); },
+                                        A.ptab_bits, x, mul);
+        return prefix_state([&](uint32_t i) {
+            return make_uint2(gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i)),
+                              gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i + 1)));
+        }, A.ptab_bits, x, mul);
+    };
+    auto offset_of = [&](uint32_t ent) __attribute__((always_inline)) {
+        return (qbase + int64_t(ent >> 12) * qstride) * CH + int64_t(ent & 4095u) - F.mis;
+    };
+
+    // Streaming-loop drain of the newest `take` entries (interior chunks only:
+    // there o + 16 <= n, so the aligned 16 bytes from (o & ~3) lie in the text
+    // and give the prefix and the 8 bytes after it).
+    auto drain_store = [&](int take) __attribute__((always_inline)) {
         wave_sync();
-        uint32_t ent[kDrain / kWave];
-        int64_t off[kDrain / kWave];
-        uint32_t x[kDrain / kWave];
+        uint32_t ent[PER_LANE];
 #pragma unroll
-        for (int r = 0; r < kDrain / kWave; ++r) {
+        for (int r = 0; r < PER_LANE; ++r) {
             // lanes past `take` repeat the first entry, so every load below is valid
             const int i = int(lane) + r * kWave;
             ent[r] = q[qlen - take + (i < take ? i : 0)];
-            off[r] = (qbase + int64_t(ent[r] >> 12) * qstride) * CH + int64_t(ent[r] & 4095u) - F.mis;
         }
         wave_sync();
         qlen -= take;
-        uint32_t rb0[kDrain / kWave], rb1[kDrain / kWave];
-        if (keep_hits) {
-            // interior chunks: o + 16 <= n, so the aligned 16 bytes from (o & ~3)
-            // lie in the text; they give the prefix and the 8 bytes after it
-            u32x4 win[kDrain / kWave];
-            uint32_t sh[kDrain / kWave];
+        u32x4 win[PER_LANE];
+        uint32_t sh[PER_LANE];
 #pragma unroll
-            for (int r = 0; r < kDrain / kWave; ++r) {
-                const uintptr_t a = reinterpret_cast<uintptr_t>(S.text + off[r]);
-                sh[r] = uint32_t(a & 3u);
-                const uint8_t *pa = reinterpret_cast<const uint8_t *>(a & ~uintptr_t(3));
-                win[r].x = gload4(pa);
-                win[r].y = gload4(pa + 4);
-                win[r].z = gload4(pa + 8);
-                win[r].w = gload4(pa + 12);
-            }
-#pragma unroll
-            for (int r = 0; r < kDrain / kWave; ++r) {
-                const uint32_t y0 = __builtin_amdgcn_alignbyte(win[r].y, win[r].x, sh[r]);
-                const uint32_t y1 = __builtin_amdgcn_alignbyte(win[r].z, win[r].y, sh[r]);
-                const uint32_t y2 = __builtin_amdgcn_alignbyte(win[r].w, win[r].z, sh[r]);
-                x[r] = K >= 3 ? (y0 & 0xFFFFFFu) : (y0 & ((1u << (8 * K)) - 1u));
-                rb0[r] = __builtin_amdgcn_alignbyte(y1, y0, uint32_t(K));
-                rb1[r] = __builtin_amdgcn_alignbyte(y2, y1, uint32_t(K));
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < kDrain / kWave; ++r) {
-                x[r] = 0;
-                rb0[r] = rb1[r] = 0;
-                if (int(lane) + r * kWave < take)
-                    for (int j = 0; j < K; ++j) x[r] |= gload1(S.text + off[r] + j) << (8 * j);
-            }
+        for (int r = 0; r < PER_LANE; ++r) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(S.text + offset_of(ent[r]));
+            sh[r] = uint32_t(a & 3u);
+            const uint8_t *pa = reinterpret_cast<const uint8_t *>(a & ~uintptr_t(3));
+            win[r].x = gload4(pa);
+            win[r].y = gload4(pa + 4);
+            win[r].z = gload4(pa + 8);
+            win[r].w = gload4(pa + 12);
         }
 #pragma unroll
-        for (int r = 0; r < kDrain / kWave; ++r) {
+        for (int r = 0; r < PER_LANE; ++r) {
+            const uint32_t y0 = __builtin_amdgcn_alignbyte(win[r].y, win[r].x, sh[r]);
+            const uint32_t y1 = __builtin_amdgcn_alignbyte(win[r].z, win[r].y, sh[r]);
+            const uint32_t y2 = __builtin_amdgcn_alignbyte(win[r].w, win[r].z, sh[r]);
+            const uint32_t x = K >= 3 ? (y0 & 0xFFFFFFu) : (y0 & ((1u << (8 * K)) - 1u));
+            const uint32_t rb0 = __builtin_amdgcn_alignbyte(y1, y0, uint32_t(K));
+            const uint32_t rb1 = __builtin_amdgcn_alignbyte(y2, y1, uint32_t(K));
             uint32_t e = 0;
             if (int(lane) + r * kWave < take) {
-                uint2 kv;
-                if (pt_lds) kv = prefix_state([&](uint32_t i) { return make_uint2(sptab[2 * i], sptab[2 * i + 1]); },
-                                              A.ptab_bits, x[r], mul);
-                else kv = prefix_state([&](uint32_t i) {
-                              return make_uint2(gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i)),
-                                                gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i + 1)));
-                          }, A.ptab_bits, x[r], mul);
+                const uint2 kv = probe(x);
                 e = kv.y;
                 // a non-final prefix state whose only child's byte differs from
-                // the text's next byte ends the walk here (interior chunks only:
-                // there rb0 holds that byte)
-                if (keep_hits && (e & kHasNext) && !(e >> 31) && (kv.x >> 24) != (rb0[r] & 0xFFu)) e = 0u;
+                // the text's next byte ends the walk at the prefix
+                if ((e & kHasNext) && !(e >> 31) && (kv.x >> 24) != (rb0 & 0xFFu)) e = 0u;
             }
             const unsigned long long hit = __ballot(e != 0u);
             if (hit == 0) continue;
             const int slot = hcount + int(rank_in(hit));
             if (e != 0u) {
-                if (keep_hits && slot < F.hit_cap) gstore16(hits + slot, ent[r], e, rb0[r], rb1[r]);
-                else walk_cold(A, S, off[r], e);
+                if (slot < F.hit_cap) gstore16(hits + slot, ent[r], e, rb0, rb1);
+                else kmin = min(kmin, ent[r] >> 12);
             }
             hcount = imin(hcount + __popcll(hit), F.hit_cap);
         }
     };
-    auto push = [&](unsigned long long m, uint32_t k) __attribute__((always_inline)) {
+    // Post-pass drain: probes with byte loads and walks the hits right here.
+    auto drain_walk = [&](int take) __attribute__((always_inline)) {
+        wave_sync();
+        uint32_t ent[PER_LANE];
+#pragma unroll
+        for (int r = 0; r < PER_LANE; ++r) {
+            const int i = int(lane) + r * kWave;
+            ent[r] = q[qlen - take + (i < take ? i : 0)];
+        }
+        wave_sync();
+        qlen -= take;
+        for (int r = 0; r < PER_LANE; ++r) {
+            if (int(lane) + r * kWave >= take) continue;
+            const int64_t o = offset_of(ent[r]);
+            uint32_t x = 0;
+            for (int j = 0; j < K; ++j) x |= gload1(S.text + o + j) << (8 * j);
+            const uint2 kv = probe(x);
+            if (kv.y) walk_rest<false, false>(A, S, A.cls, o, kv.y, make_uint2(0u, 0u), nullptr);
+        }
+    };
+    auto push = [&](unsigned long long m, uint32_t k, auto &&drain) __attribute__((always_inline)) {
         while (true) {
             const unsigned long long act = __ballot(m != 0);
             if (act == 0) break;
@@ -517,21 +541,32 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         while (c < F.c_hi) {
             const int64_t c1 = c + nw;
             if (c1 < F.c_hi) load_interior<SEGS>(F, c1, lane, rb);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(ra, lane, sfilt, mul), k++);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(ra, lane, sfilt, mul), k++, drain_store);
             c = c1;
             if (c >= F.c_hi) break;
             const int64_t c2 = c + nw;
             if (c2 < F.c_hi) load_interior<SEGS>(F, c2, lane, ra);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(rb, lane, sfilt, mul), k++);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(rb, lane, sfilt, mul), k++, drain_store);
             c = c2;
         }
-        while (qlen > 0) drain(imin(qlen, kDrain));
+        while (qlen > 0) drain_store(imin(qlen, kDrain));
     }
-    if (lane == 0) F.hit_count[w] = hcount;
+    kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
+    if (lane == 0) {
+        F.hit_count[w] = hcount;
+        F.hit_kmin[w] = kmin;
+    }
 
-    // chunks overlapping an end of the text: [0, p0) and [p1, n_chunks); their
-    // hits are walked here
-    keep_hits = false;
+    // post-pass 1: interior chunks from the first step that lost a hit
+    for (uint32_t k = kmin; kmin != 0xFFFFFFFFu; ++k) {
+        const int64_t c = F.c_lo + w + int64_t(k) * nw;
+        if (c >= F.c_hi) break;
+        ChunkRegs<SEGS> r;
+        load_interior<SEGS>(F, c, lane, r);
+        push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(r, lane, sfilt, mul), k, drain_walk);
+        while (qlen > 0) drain_walk(imin(qlen, kDrain));
+    }
+    // post-pass 2: chunks overlapping an end of the text: [0, p0) and [p1, n_chunks)
     const int64_t p0 = lmin(F.c_lo, F.n_chunks);
     const int64_t p1 = lmax(F.c_hi, F.c_lo);
     const int64_t n_partial = p0 + (F.n_chunks - p1);
@@ -547,8 +582,8 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         }
         qbase = pc;
         qstride = 0;
-        push(m, 0);
-        while (qlen > 0) drain(imin(qlen, kDrain));
+        push(m, 0, drain_walk);
+        while (qlen > 0) drain_walk(imin(qlen, kDrain));
     }
 }
 
@@ -558,6 +593,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
 struct WalkLaunch {
     const uint4 *hits;
     const int32_t *hit_count;
+    const uint32_t *hit_kmin;
     int32_t hit_cap;
     int64_t regions;        // streaming waves
     int64_t c_lo, nw;       // first interior chunk, streaming waves (chunk stride)
@@ -590,6 +626,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const DevAut A, const 
         while (first[j + 1] <= i) ++j;          // region of flat index i
         const int64_t region = r0 + j;
         const uint4 rec = W.hits[region * W.hit_cap + (i - first[j])];
+        if ((rec.x >> 12) >= W.hit_kmin[region]) continue;   // walked by the streaming kernel
         const int64_t chunk = W.c_lo + region + int64_t(rec.x >> 12) * W.nw;
         const int64_t o = chunk * W.chunk_bytes + int64_t(rec.x & 4095u) - W.mis;
         walk_rest<true, true>(A, S, scls, o, rec.y, make_uint2(rec.z, rec.w), &st);
@@ -803,12 +840,13 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
     if (cfg.policy == AC_POLICY_FILTERED) {
         FilteredGeom G = filtered_geom(a, S.text, S.n, cfg);
         FilterLaunch &F = G.F;
-        if (!hs.hits || !hs.count || hs.regions < G.waves || hs.cap <= 0) {
+        if (!hs.hits || !hs.count || !hs.kmin || hs.regions < G.waves || hs.cap <= 0) {
             err = "scan scratch too small for the launch";
             return AC_EINVAL;
         }
         F.hits = hs.hits;
         F.hit_count = hs.count;
+        F.hit_kmin = hs.kmin;
         F.hit_cap = hs.cap;
         const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
         // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
@@ -820,6 +858,7 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         WalkLaunch W;
         W.hits = hs.hits;
         W.hit_count = hs.count;
+        W.hit_kmin = hs.kmin;
         W.hit_cap = hs.cap;
         W.regions = G.waves;
         W.c_lo = F.c_lo;

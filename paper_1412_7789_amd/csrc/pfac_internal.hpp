@@ -132,6 +132,7 @@ uint32_t prefix_hash(uint32_t x, uint32_t mul);
 struct HitScratch {
     uint4 *hits = nullptr;         // [regions * cap]
     int32_t *count = nullptr;      // [regions]
+    uint32_t *kmin = nullptr;      // [regions]
     int64_t regions = 0;
     int32_t cap = 0;
 };

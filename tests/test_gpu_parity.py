@@ -162,3 +162,17 @@ def test_errors_are_reported():
     t = torch.zeros(10, dtype=torch.uint8, device="cuda")
     with pytest.raises(pf.PfacError):
         a.count(t, launch=pf.launch_config(block=100))
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_hit_region_overflow(stride):
+    """A periodic text where a third of all offsets match fills every wave's
+    hit region many times over, so the streaming kernel's post-pass walks the
+    chunks whose hits were dropped (and the walk kernel skips their stored
+    records)."""
+    kws = [b"abcab", b"cabca", b"zzzz"]
+    text = np.frombuffer(b"abc" * (16 << 20 // 3), dtype=np.uint8)
+    text = np.ascontiguousarray(text[: 16 << 20])
+    say("overflow", stride, len(text))
+    cfg = pf.launch_config(policy=1, stride=stride, segs=4)
+    assert_same(gpu_match(kws, text, launch=cfg), oracle_match(kws, text), f"overflow stride {stride}")
