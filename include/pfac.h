@@ -198,8 +198,13 @@ int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
 const char *ac_last_error(void);
 
 /* Scan-kernel milliseconds of this thread's last synchronous call made with
- * AC_LAUNCH_TIME_SCAN (negative if none). */
+ * AC_LAUNCH_TIME_SCAN (negative if none): all kernels of the scan. */
 float ac_last_scan_ms(void);
+
+/* The same call's split for the filtered policy: *stream_ms = the streaming
+ * (filter + probe) kernel, *walk_ms = the walk kernel; both negative if the
+ * last timed call used another policy or none was made. */
+void ac_last_scan_split(float *stream_ms, float *walk_ms);
 
 /* ---- measurement probe -------------------------------------------------------- */
 /*

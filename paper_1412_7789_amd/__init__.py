@@ -11,4 +11,4 @@ from ._lib import (  # noqa: F401
     AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19,
     AC_LAUNCH_TIME_SCAN, EXPORTS, LIB_PATH, PfacError, load,
 )
-from .api import Automaton, Plan, last_scan_ms, launch_config, probe_read, sorted_pairs  # noqa: F401
+from .api import Automaton, Plan, last_scan_ms, last_scan_split, launch_config, probe_read, sorted_pairs  # noqa: F401

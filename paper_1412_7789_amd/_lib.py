@@ -20,7 +20,7 @@ EXPORTS = [
     "ac_build", "ac_build_csr", "ac_free", "ac_match", "ac_match_ex", "ac_match_async",
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
-    "ac_plan_free", "ac_last_scan_ms", "ac_probe_read",
+    "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read",
 ]
 AC_LAUNCH_TIME_SCAN = 1
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_plan_hash": (u32, [vp, u32]),
         "ac_plan_free": (None, [vp]),
         "ac_last_scan_ms": (ctypes.c_float, []),
+        "ac_last_scan_split": (None, [vp, vp]),
         "ac_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():

@@ -43,6 +43,13 @@ def last_scan_ms() -> float:
     return float(L.load().ac_last_scan_ms())
 
 
+def last_scan_split() -> Tuple[float, float]:
+    """(streaming kernel ms, walk kernel ms) of the same last timed call."""
+    a, b = ctypes.c_float(), ctypes.c_float()
+    L.load().ac_last_scan_split(ctypes.byref(a), ctypes.byref(b))
+    return float(a.value), float(b.value)
+
+
 def probe_read(buf, out, stream=None) -> None:
     """Enqueue the read-bandwidth probe over a uint8 CUDA tensor (16-byte
     aligned, length a multiple of 16); ``out`` is a 1-element int32 tensor."""

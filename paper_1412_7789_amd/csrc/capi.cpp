@@ -19,6 +19,7 @@ namespace {
 
 thread_local std::string g_err;
 thread_local float g_scan_ms = -1.0f;
+thread_local float g_stream_ms = -1.0f, g_walk_ms = -1.0f;
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -34,7 +35,7 @@ int hip_fail(const char *what, hipError_t e) {
 struct CountSlot {
     unsigned long long *d = nullptr;
     unsigned long long *h = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // scan timing, created on first use
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;   // scan timing, created on first use
     HitScratch hs;                             // hit regions of the filtered policy
 };
 std::mutex g_slots_mu;
@@ -72,7 +73,8 @@ int count_slot(int device, hipStream_t stream, CountSlot &out, int64_t regions) 
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
     e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocDefault);
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
-    if ((e = hipEventCreate(&s.ev0)) != hipSuccess || (e = hipEventCreate(&s.ev1)) != hipSuccess)
+    if ((e = hipEventCreate(&s.ev0)) != hipSuccess || (e = hipEventCreate(&s.ev1)) != hipSuccess ||
+        (e = hipEventCreate(&s.evm)) != hipSuccess)
         return hip_fail("hipEventCreate", e);
     int rc = ensure_hits(s, regions);
     g_slots[key] = s;
@@ -226,7 +228,7 @@ int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch &cfg, bool batch,
         hipError_t e = hipEventRecord(timing->ev0, stream);
         if (e != hipSuccess) return hip_fail("hipEventRecord", e);
     }
-    rc = launch_scan(a, S, cfg, hs, stream, err);
+    rc = launch_scan(a, S, cfg, hs, stream, err, timing ? timing->evm : nullptr);
     if (rc) return fail(rc, err);
     if (timing) {
         hipError_t e = hipEventRecord(timing->ev1, stream);
@@ -242,7 +244,7 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     int rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg));
     if (rc) return rc;
     const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN);
-    g_scan_ms = -1.0f;
+    g_scan_ms = g_stream_ms = g_walk_ms = -1.0f;
     rc = enqueue(a, S, cfg, batch, slot.d, slot.hs, stream, timed ? &slot : nullptr);
     if (rc) return rc;
     hipError_t e = hipMemcpyAsync(slot.h, slot.d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
@@ -253,6 +255,14 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         float ms = -1.0f;
         if ((e = hipEventElapsedTime(&ms, slot.ev0, slot.ev1)) != hipSuccess) return hip_fail("hipEventElapsedTime", e);
         g_scan_ms = ms;
+        if (cfg.policy == AC_POLICY_FILTERED) {
+            float a0 = -1.0f, a1 = -1.0f;
+            if ((e = hipEventElapsedTime(&a0, slot.ev0, slot.evm)) != hipSuccess ||
+                (e = hipEventElapsedTime(&a1, slot.evm, slot.ev1)) != hipSuccess)
+                return hip_fail("hipEventElapsedTime", e);
+            g_stream_ms = a0;
+            g_walk_ms = a1;
+        }
     }
     return int64_t(*slot.h);
 }
@@ -344,6 +354,11 @@ extern "C" {
 const char *ac_last_error(void) { return g_err.c_str(); }
 
 float ac_last_scan_ms(void) { return g_scan_ms; }
+
+void ac_last_scan_split(float *stream_ms, float *walk_ms) {
+    if (stream_ms) *stream_ms = g_stream_ms;
+    if (walk_ms) *walk_ms = g_walk_ms;
+}
 
 int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t stream) {
     if (!d_buf || !d_out || n < 0 || (n % 16) || (reinterpret_cast<uintptr_t>(d_buf) % 16))

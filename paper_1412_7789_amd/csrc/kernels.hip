@@ -833,7 +833,7 @@ int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, cons
 }
 
 int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err) {
+                hipStream_t stream, std::string &err, hipEvent_t mid_event) {
     if (S.n <= 0) return AC_OK;
     const Plan &P = a->host;
     hipError_t e = hipSuccess;
@@ -855,6 +855,10 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         hipLaunchKernelGGL(fn, dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
         e = hipGetLastError();
         if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
+        if (mid_event && (e = hipEventRecord(mid_event, stream)) != hipSuccess) {
+            err = std::string("hipEventRecord: ") + hipGetErrorString(e);
+            return AC_EHIP;
+        }
         WalkLaunch W;
         W.hits = hs.hits;
         W.hit_count = hs.count;

@@ -140,8 +140,9 @@ constexpr int32_t kHitCap = 1024;
 
 // kernels.hip
 int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
+// mid_event (may be null) is recorded between the filtered policy's two kernels.
 int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err);
+                hipStream_t stream, std::string &err, hipEvent_t mid_event = nullptr);
 int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
                 hipStream_t stream, std::string &err);
 void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg);
