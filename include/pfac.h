@@ -111,9 +111,10 @@ typedef struct {
     int32_t reserved[4];
 } ac_launch;
 
-/* Record HIP events on the call's stream immediately before and after the
- * scan kernel; a synchronous call then leaves the kernel's duration for
- * ac_last_scan_ms() in the calling thread. */
+/* Time the scan's kernels with HIP events taken from their own dispatch
+ * packets (start and end of each kernel, no launch gaps); a synchronous call
+ * then leaves the durations for ac_last_scan_ms() / ac_last_scan_split() in
+ * the calling thread. */
 #define AC_LAUNCH_TIME_SCAN 1
 
 /*
@@ -124,8 +125,12 @@ typedef struct {
  * the caller may retry with a larger buffer.  matches == NULL counts only.
  * len == 0 returns 0.  d_text may have any alignment.
  * The call is stream-ordered on `stream` and synchronises it to return the
- * count.  Errors: AC_EINVAL (NULL automaton, NULL text with len > 0, len < 0,
- * capacity < 0, NULL arrays with capacity > 0), AC_EHIP.
+ * count.  The library keeps per-(device, stream) scratch (a count word and
+ * the filtered policy's hit regions), allocated on the stream's first call
+ * and grown when a longer text needs more; calls on one stream must come
+ * from one thread at a time.  Errors: AC_EINVAL (NULL automaton, NULL text
+ * with len > 0, len < 0, capacity < 0, NULL arrays with capacity > 0),
+ * AC_ENOMEM, AC_EHIP.
  */
 int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len,
                  const ac_matches *matches, hipStream_t stream);
@@ -137,7 +142,10 @@ int64_t ac_match_ex(const ac_automaton *a, const uint8_t *d_text, int64_t len,
 /*
  * Asynchronous form: enqueues the scan on `stream` and writes the match count
  * to d_count (device int64) without synchronising; returns AC_OK or an error.
- * It makes no allocation and no memset, so it may be captured in a HIP graph.
+ * It clears d_count with a kernel (no memset).  Once the stream's scratch has
+ * been sized by an earlier call on a text at least as long, it allocates
+ * nothing, so it may then be captured in a HIP graph; replays of captured
+ * scans that share a stream's scratch must not overlap.
  */
 int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len,
                    const ac_matches *matches, const ac_launch *launch,
@@ -198,12 +206,13 @@ int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
 const char *ac_last_error(void);
 
 /* Scan-kernel milliseconds of this thread's last synchronous call made with
- * AC_LAUNCH_TIME_SCAN (negative if none): all kernels of the scan. */
+ * AC_LAUNCH_TIME_SCAN (negative if none or if the text was empty): from the
+ * start of the first scan kernel to the end of the last one. */
 float ac_last_scan_ms(void);
 
-/* The same call's split for the filtered policy: *stream_ms = the streaming
- * (filter + probe) kernel, *walk_ms = the walk kernel; both negative if the
- * last timed call used another policy or none was made. */
+/* The same call's split: *stream_ms = the streaming (filter + probe) kernel
+ * of the filtered policy or the direct kernel, *walk_ms = the walk kernel
+ * (0 for the direct policy); both negative if no timed call was made. */
 void ac_last_scan_split(float *stream_ms, float *walk_ms);
 
 /* ---- measurement probe -------------------------------------------------------- */

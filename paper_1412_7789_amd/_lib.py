@@ -22,6 +22,13 @@ EXPORTS = [
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read",
 ]
+# every symbol include/pfac_serve.h declares
+SERVE_EXPORTS = [
+    "ac_server_create", "ac_server_destroy", "ac_server_add_automaton", "ac_server_submit",
+    "ac_server_wait", "ac_server_poll", "ac_server_release", "ac_server_replay", "ac_server_get_stats",
+    "ac_serve_charge", "ac_serve_plan",
+]
+AC_SERVE_BATCHED, AC_SERVE_FIFO = 0, 1
 AC_LAUNCH_TIME_SCAN = 1
 
 
@@ -63,6 +70,27 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("max_batch_bytes", ctypes.c_int64), ("max_batch_texts", ctypes.c_int32),
+                ("matches_per_kib", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batch_requests", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("offset", ctypes.POINTER(ctypes.c_int64)), ("pattern_id", ctypes.POINTER(ctypes.c_int32)),
+                ("submit_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("batches", ctypes.c_int64), ("text_bytes", ctypes.c_int64),
+                ("admission_waits", ctypes.c_int64), ("rescans", ctypes.c_int64), ("peak_charged", ctypes.c_int64),
+                ("max_batch_requests", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 
 
@@ -71,6 +99,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # torch's HIP runtime must be the one loaded: the library then shares
+        # it (and its device context) instead of loading a second copy
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
@@ -97,6 +131,17 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_last_scan_ms": (ctypes.c_float, []),
         "ac_last_scan_split": (None, [vp, vp]),
         "ac_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
+        "ac_server_create": (ctypes.c_int, [vp, vp]),
+        "ac_server_destroy": (None, [vp]),
+        "ac_server_add_automaton": (ctypes.c_int, [vp, vp]),
+        "ac_server_submit": (i64, [vp, i32, vp, i64]),
+        "ac_server_wait": (ctypes.c_int, [vp, i64, vp]),
+        "ac_server_poll": (ctypes.c_int, [vp, i64, vp]),
+        "ac_server_release": (None, [vp, i64]),
+        "ac_server_replay": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp, vp]),
+        "ac_server_get_stats": (ctypes.c_int, [vp, vp]),
+        "ac_serve_charge": (i64, [vp, i64]),
+        "ac_serve_plan": (i32, [vp, i32, vp, vp, i64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -201,6 +201,25 @@ class Automaton:
                                                ctypes.byref(launch) if launch is not None else None,
                                                _stream_ptr(stream)), "ac_match_batch")
 
+    def match_batch_async(self, texts, text_offsets, text_ids, offsets, pattern_ids, d_count, per_text=None,
+                          launch: Optional[L.Launch] = None, stream=None, total_bytes: Optional[int] = None) -> None:
+        """Enqueue a batch scan only; the total count lands in ``d_count``
+        (int64 CUDA tensor).  Capturable in a HIP graph once the stream has
+        run a batch at least as large."""
+        _check_text(texts)
+        n_texts = text_offsets.numel() - 1
+        total = texts.numel() if total_bytes is None else total_bytes
+        cap = min(offsets.numel(), pattern_ids.numel(), text_ids.numel())
+        m = L.BatchMatches(ctypes.c_void_p(text_ids.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                           ctypes.c_void_p(pattern_ids.data_ptr()), cap,
+                           ctypes.c_void_p(per_text.data_ptr()) if per_text is not None else None)
+        L.check(L.load().ac_match_batch_async(self._h, ctypes.c_void_p(texts.data_ptr()),
+                                              ctypes.c_void_p(text_offsets.data_ptr()), n_texts, total,
+                                              ctypes.byref(m),
+                                              ctypes.byref(launch) if launch is not None else None,
+                                              ctypes.c_void_p(d_count.data_ptr()), _stream_ptr(stream)),
+                "ac_match_batch_async")
+
     def match_batch(self, texts, text_offsets, capacity: Optional[int] = None,
                     launch: Optional[L.Launch] = None, stream=None):
         """Match a packed batch; returns (text_ids, offsets, pattern_ids, per_text_count)."""

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpfac.so")
-SOURCES = ["plan.cpp", "kernels.hip", "capi.cpp"]
+SOURCES = ["plan.cpp", "kernels.hip", "capi.cpp", "serve.cpp"]
 ARCH = os.environ.get("PFAC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -49,7 +49,7 @@ def build(out: str = LIB, verbose: bool = False) -> str:
             print(warn, file=sys.stderr)
         objs.append(obj)
     tmp = out + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     os.replace(tmp, out)
     return out

@@ -31,15 +31,20 @@ int hip_fail(const char *what, hipError_t e) {
 }
 
 // One device count word and one pinned host word per (device, stream),
-// allocated on first use and kept for the life of the process.
+// allocated on first use and kept for the life of the process.  The
+// synchronous calls never clear the device word: it only grows, the pinned
+// word holds its value after the last such call, and a scan numbers its
+// matches from that value on (ScanArgs::count_base).  The batch calls clear
+// it with their per-text counts.
 struct CountSlot {
     unsigned long long *d = nullptr;
     unsigned long long *h = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;   // scan timing, created on first use
+    bool stale = false;                        // a failed call may have left *d != *h
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // kernel timing: scan start/stop, walk start/stop
     HitScratch hs;                             // hit regions of the filtered policy
 };
 std::mutex g_slots_mu;
-std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
+std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;   // entries are never erased
 
 // Grows the slot's hit regions to at least `regions` (never shrinks).
 int ensure_hits(CountSlot &s, int64_t regions) {
@@ -59,27 +64,28 @@ int ensure_hits(CountSlot &s, int64_t regions) {
     return AC_OK;
 }
 
-int count_slot(int device, hipStream_t stream, CountSlot &out, int64_t regions) {
+// The slot of (device, stream), created on first use; the pointer stays valid.
+int count_slot(int device, hipStream_t stream, CountSlot **out, int64_t regions) {
     std::lock_guard<std::mutex> lk(g_slots_mu);
     auto key = std::make_pair(device, stream);
     auto it = g_slots.find(key);
     if (it != g_slots.end()) {
-        int rc = ensure_hits(it->second, regions);
-        out = it->second;
-        return rc;
+        *out = &it->second;
+        return ensure_hits(it->second, regions);
     }
     CountSlot s;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
     e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocDefault);
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
-    if ((e = hipEventCreate(&s.ev0)) != hipSuccess || (e = hipEventCreate(&s.ev1)) != hipSuccess ||
-        (e = hipEventCreate(&s.evm)) != hipSuccess)
-        return hip_fail("hipEventCreate", e);
-    int rc = ensure_hits(s, regions);
-    g_slots[key] = s;
-    out = s;
-    return rc;
+    *s.h = 0;
+    s.stale = true;                            // cleared by the first call
+    for (auto &ev : s.ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail("hipEventCreate", e);
+    CountSlot &slot = g_slots[key];
+    slot = s;
+    *out = &slot;
+    return ensure_hits(slot, regions);
 }
 
 int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -218,53 +224,69 @@ ac_launch resolved(const ac_automaton *a, const ScanArgs &S, const ac_launch *la
     return cfg;
 }
 
-int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch &cfg, bool batch, unsigned long long *d_count,
-            const HitScratch &hs, hipStream_t stream, const CountSlot *timing = nullptr) {
+// Enqueue the scan of one text or a batch.  `clear` first zeroes *d_count
+// (and the batch's per-text counts); otherwise matches are numbered from
+// S.count_base.
+int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch &cfg, bool batch, bool clear,
+            unsigned long long *d_count, const HitScratch &hs, hipStream_t stream,
+            const KernelTiming *timing = nullptr) {
     S.count = d_count;
     std::string err;
-    int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
-    if (rc) return fail(rc, err);
-    if (timing) {
-        hipError_t e = hipEventRecord(timing->ev0, stream);
-        if (e != hipSuccess) return hip_fail("hipEventRecord", e);
+    if (clear) {
+        S.count_base = 0;
+        int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
+        if (rc) return fail(rc, err);
     }
-    rc = launch_scan(a, S, cfg, hs, stream, err, timing ? timing->evm : nullptr);
-    if (rc) return fail(rc, err);
-    if (timing) {
-        hipError_t e = hipEventRecord(timing->ev1, stream);
-        if (e != hipSuccess) return hip_fail("hipEventRecord", e);
-    }
-    return AC_OK;
+    int rc = launch_scan(a, S, cfg, hs, stream, err, timing);
+    return rc ? fail(rc, err) : AC_OK;
 }
 
 int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, bool batch, hipStream_t stream) {
     if (batch && launch && launch->policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
     const ac_launch cfg = resolved(a, S, launch, batch);
-    CountSlot slot;
-    int rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg));
+    CountSlot *slot = nullptr;
+    int rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg));
     if (rc) return rc;
-    const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN);
+    const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN) && S.n > 0;
     g_scan_ms = g_stream_ms = g_walk_ms = -1.0f;
-    rc = enqueue(a, S, cfg, batch, slot.d, slot.hs, stream, timed ? &slot : nullptr);
+    KernelTiming T;
+    if (timed) {
+        T.scan0 = slot->ev[0];
+        T.scan1 = slot->ev[1];
+        if (cfg.policy == AC_POLICY_FILTERED) {
+            T.walk0 = slot->ev[2];
+            T.walk1 = slot->ev[3];
+        }
+    }
+    // a batch clears the word (its per-text counts need a clearing kernel anyway)
+    const bool clear = batch || slot->stale;
+    const unsigned long long base = clear ? 0ull : *slot->h;
+    S.count_base = base;
+    if (S.n == 0 && !clear) return 0;              // nothing to scan, nothing to clear
+    slot->stale = true;
+    rc = enqueue(a, S, cfg, batch, clear, slot->d, slot->hs, stream, timed ? &T : nullptr);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(slot.h, slot.d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
+    hipError_t e = hipMemcpyAsync(slot->h, slot->d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
-    if (timed && S.n > 0) {
+    slot->stale = false;
+    if (timed) {
         float ms = -1.0f;
-        if ((e = hipEventElapsedTime(&ms, slot.ev0, slot.ev1)) != hipSuccess) return hip_fail("hipEventElapsedTime", e);
-        g_scan_ms = ms;
-        if (cfg.policy == AC_POLICY_FILTERED) {
-            float a0 = -1.0f, a1 = -1.0f;
-            if ((e = hipEventElapsedTime(&a0, slot.ev0, slot.evm)) != hipSuccess ||
-                (e = hipEventElapsedTime(&a1, slot.evm, slot.ev1)) != hipSuccess)
+        if ((e = hipEventElapsedTime(&ms, T.scan0, T.scan1)) != hipSuccess) return hip_fail("hipEventElapsedTime", e);
+        g_scan_ms = g_stream_ms = ms;
+        if (T.walk0) {
+            float w = -1.0f, all = -1.0f;
+            if ((e = hipEventElapsedTime(&w, T.walk0, T.walk1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&all, T.scan0, T.walk1)) != hipSuccess)
                 return hip_fail("hipEventElapsedTime", e);
-            g_stream_ms = a0;
-            g_walk_ms = a1;
+            g_walk_ms = w;
+            g_scan_ms = all;
+        } else {
+            g_walk_ms = 0.0f;
         }
     }
-    return int64_t(*slot.h);
+    return int64_t(*slot->h - base);
 }
 
 int check_single(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *m) {
@@ -348,6 +370,8 @@ int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const 
 }
 
 }  // namespace
+
+int pfac::report_error(int code, const std::string &msg) { return fail(code, msg); }
 
 extern "C" {
 
@@ -435,9 +459,9 @@ int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len, co
     if (!d_count) return fail(AC_EINVAL, "ac_match_async: NULL count pointer");
     const ScanArgs S = single_args(d_text, len, matches);
     const ac_launch cfg = resolved(a, S, launch, false);
-    CountSlot slot;
-    if ((rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
-    return enqueue(a, S, cfg, false, reinterpret_cast<unsigned long long *>(d_count), slot.hs, stream);
+    CountSlot *slot = nullptr;
+    if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    return enqueue(a, S, cfg, false, true, reinterpret_cast<unsigned long long *>(d_count), slot->hs, stream);
 }
 
 int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets,
@@ -460,9 +484,9 @@ int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts, const in
     if (launch && launch->policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
     const ScanArgs S = batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches);
     const ac_launch cfg = resolved(a, S, launch, true);
-    CountSlot slot;
-    if ((rc = count_slot(a->device, stream, slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
-    return enqueue(a, S, cfg, true, reinterpret_cast<unsigned long long *>(d_count), slot.hs, stream);
+    CountSlot *slot = nullptr;
+    if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    return enqueue(a, S, cfg, true, true, reinterpret_cast<unsigned long long *>(d_count), slot->hs, stream);
 }
 
 // ---- host-side inspection -----------------------------------------------------

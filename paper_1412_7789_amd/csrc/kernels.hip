@@ -25,6 +25,7 @@
 // slots, each lane writes at its rank.  The returned count is exact even when
 // the output buffer is too small (only `cap` entries are written).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdio>
@@ -109,7 +110,7 @@ __device__ __forceinline__ void emit(const DevAut &A, const ScanArgs &S, int64_t
         unsigned long long base = 0;
         if (rank == 0) base = atomicAdd(S.count, static_cast<unsigned long long>(__popcll(act)));
         base = readlane64(base, leader);
-        const unsigned long long idx = base + rank;
+        const unsigned long long idx = base + rank - S.count_base;
         if (idx < static_cast<unsigned long long>(S.cap)) {
             S.out_off[idx] = off;
             S.out_pid[idx] = A.out_pid[k];
@@ -143,7 +144,7 @@ __device__ __forceinline__ void emit_staged(const DevAut &A, const ScanArgs &S, 
             if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
         } else {
             // stage full: this id goes out directly (one atomic)
-            const unsigned long long idx = atomicAdd(S.count, 1ull);
+            const unsigned long long idx = atomicAdd(S.count, 1ull) - S.count_base;
             if (idx < static_cast<unsigned long long>(S.cap)) {
                 S.out_off[idx] = off;
                 S.out_pid[idx] = A.out_pid[k];
@@ -158,7 +159,7 @@ __device__ __forceinline__ void emit_staged(const DevAut &A, const ScanArgs &S, 
 __device__ __forceinline__ void flush_stage(const ScanArgs &S, MatchStage *st) {
     __syncthreads();
     const int32_t n = imin(st->n, kStageCap);
-    if (threadIdx.x == 0) st->base = n ? atomicAdd(S.count, static_cast<unsigned long long>(n)) : 0ull;
+    if (threadIdx.x == 0) st->base = n ? atomicAdd(S.count, static_cast<unsigned long long>(n)) - S.count_base : 0ull;
     __syncthreads();
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
         const unsigned long long idx = st->base + unsigned(i);
@@ -753,6 +754,14 @@ FilteredGeom filtered_geom(const ac_automaton *a, const uint8_t *text, int64_t n
     return G;
 }
 
+// Launch through hipExtLaunchKernel when start/stop events are wanted (they
+// are then taken from the kernel's own dispatch packet), else hipLaunchKernel.
+hipError_t launch_timed(const void *fn, dim3 grid, dim3 block, void **args, size_t lds, hipStream_t stream,
+                        hipEvent_t start, hipEvent_t stop) {
+    if (start || stop) return hipExtLaunchKernel(fn, grid, block, args, lds, stream, start, stop, 0);
+    return hipLaunchKernel(fn, grid, block, args, lds, stream);
+}
+
 std::mutex g_attr_mu;
 
 void allow_lds(const void *fn, int64_t bytes) {
@@ -833,7 +842,9 @@ int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, cons
 }
 
 int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err, hipEvent_t mid_event) {
+                hipStream_t stream, std::string &err, const KernelTiming *timing) {
+    const KernelTiming none;
+    const KernelTiming &T = timing ? *timing : none;
     if (S.n <= 0) return AC_OK;
     const Plan &P = a->host;
     hipError_t e = hipSuccess;
@@ -852,13 +863,12 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
         if (interior / G.waves >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
         FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs, cfg.stride);
-        hipLaunchKernelGGL(fn, dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), 0, stream, a->dev, S, F);
-        e = hipGetLastError();
+        DevAut A = a->dev;
+        ScanArgs SA = S;
+        void *fargs[] = {&A, &SA, &F};
+        e = launch_timed(reinterpret_cast<const void *>(fn), dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), fargs, 0,
+                         stream, T.scan0, T.scan1);
         if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
-        if (mid_event && (e = hipEventRecord(mid_event, stream)) != hipSuccess) {
-            err = std::string("hipEventRecord: ") + hipGetErrorString(e);
-            return AC_EHIP;
-        }
         WalkLaunch W;
         W.hits = hs.hits;
         W.hit_count = hs.count;
@@ -870,8 +880,9 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         W.chunk_bytes = int64_t(cfg.segs) * kSegBytes;
         W.mis = F.mis;
         const int64_t wblocks = (G.waves + kWalkRegions - 1) / kWalkRegions;
-        hipLaunchKernelGGL(walk_kernel, dim3(unsigned(wblocks)), dim3(kWalkBlock), 0, stream, a->dev, S, W);
-        e = hipGetLastError();
+        void *wargs[] = {&A, &SA, &W};
+        e = launch_timed(reinterpret_cast<const void *>(walk_kernel), dim3(unsigned(wblocks)), dim3(kWalkBlock), wargs,
+                         0, stream, T.walk0, T.walk1);
     } else if (cfg.policy == AC_POLICY_DIRECT) {
         if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }
         DirectLaunch L;
@@ -884,8 +895,11 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         if (lds > a->lds_per_block) { err = "direct policy: tile and table exceed LDS"; return AC_ENOTSUP; }
         auto fn = lds_table ? direct_kernel<true> : direct_kernel<false>;
         allow_lds(reinterpret_cast<const void *>(fn), lds);
-        hipLaunchKernelGGL(fn, dim3(unsigned(grid)), dim3(unsigned(cfg.block)), size_t(lds), stream, a->dev, S, L);
-        e = hipGetLastError();
+        DevAut A = a->dev;
+        ScanArgs SA = S;
+        void *dargs[] = {&A, &SA, &L};
+        e = launch_timed(reinterpret_cast<const void *>(fn), dim3(unsigned(grid)), dim3(unsigned(cfg.block)), dargs,
+                         size_t(lds), stream, T.scan0, T.scan1);
     } else {
         err = "unknown policy";
         return AC_EINVAL;

@@ -103,6 +103,7 @@ struct ScanArgs {
     int32_t *out_tid;              // batch only
     int64_t cap;                   // 0 = count only
     unsigned long long *count;
+    unsigned long long count_base; // value of *count before this scan: match i goes to index i - base
     int64_t *per_text;             // batch only, may be null
 };
 
@@ -140,11 +141,19 @@ constexpr int32_t kHitCap = 1024;
 
 // kernels.hip
 int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
-// mid_event (may be null) is recorded between the filtered policy's two kernels.
+// Start/stop events of the scan's kernels (each pair may be null): the
+// streaming (or direct) kernel and the walk kernel, taken from their own
+// dispatch packets so that they time the kernel alone.
+struct KernelTiming {
+    hipEvent_t scan0 = nullptr, scan1 = nullptr, walk0 = nullptr, walk1 = nullptr;
+};
 int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err, hipEvent_t mid_event = nullptr);
+                hipStream_t stream, std::string &err, const KernelTiming *timing = nullptr);
 int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
                 hipStream_t stream, std::string &err);
 void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg);
+
+// Sets the calling thread's ac_last_error() message; returns `code`.
+int report_error(int code, const std::string &msg);
 int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t stream, std::string &err);
 }  // namespace pfac

@@ -187,3 +187,46 @@ def test_batch_edge_cases():
         et, eo, ep = batch_expected(kws, flat, offs)
         assert (batch_key(tid, off, pid) == batch_key(et, eo, ep)).all(), shift
         assert (per == np.bincount(et, minlength=len(texts))).all()
+
+
+def test_batch_graph_replays_match_eager():
+    """The asynchronous batch call captured in a HIP graph: every replay, with
+    eager calls on other streams in between, gives the eager result."""
+    w = config_batched()
+    n = 300
+    end = int(w.offsets[n])
+    texts, offsets = w.texts[:end], w.offsets[:n + 1]
+    a = pf.Automaton(w.keywords)
+    d_texts = torch.from_numpy(texts).cuda()
+    d_offs = torch.from_numpy(offsets).cuda()
+    et, eo, ep, eper = (x.cpu().numpy() for x in a.match_batch(d_texts, d_offs))
+    exp_key = batch_key(et, eo, ep)
+    bt, bo, bp = batch_expected(w.keywords, texts, offsets)
+    assert (batch_key(bt, bo, bp) == exp_key).all()
+    cap = len(et) + 16
+    tid = torch.empty(cap, dtype=torch.int32, device="cuda")
+    off = torch.empty(cap, dtype=torch.int64, device="cuda")
+    pid = torch.empty(cap, dtype=torch.int32, device="cuda")
+    per = torch.empty(n, dtype=torch.int64, device="cuda")
+    d_count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.match_batch_async(d_texts, d_offs, tid, off, pid, d_count, per, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.match_batch_async(d_texts, d_offs, tid, off, pid, d_count, per, stream=s)
+    for r in range(4):
+        say("graph replay", r)
+        tid.fill_(-1)
+        per.fill_(-7)
+        d_count.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        k = int(d_count.item())
+        assert k == len(et)
+        got = batch_key(tid[:k].cpu().numpy(), off[:k].cpu().numpy(), pid[:k].cpu().numpy())
+        assert (got == exp_key).all()
+        assert (per.cpu().numpy() == eper).all()
+        # eager work on the default stream between replays
+        assert a.count(d_texts[: int(offsets[1])]) == int(eper[0])

@@ -176,3 +176,31 @@ def test_hit_region_overflow(stride):
     say("overflow", stride, len(text))
     cfg = pf.launch_config(policy=1, stride=stride, segs=4)
     assert_same(gpu_match(kws, text, launch=cfg), oracle_match(kws, text), f"overflow stride {stride}")
+
+
+def test_interleaved_call_kinds_share_a_stream():
+    """Synchronous single-text calls number their matches from the stream's
+    running count; batch and asynchronous calls in between must not disturb
+    that numbering."""
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    t = torch.from_numpy(w.text).cuda()
+    exp = oracle_match(w.keywords, w.text)
+    n = len(exp[0])
+    flat = torch.from_numpy(np.concatenate([w.text[:5000], w.text[:3000]])).cuda()
+    offs = torch.tensor([0, 5000, 8000], dtype=torch.int64, device="cuda")
+    d_count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for round_ in range(3):
+        say("interleave", round_)
+        off1, pid1 = a.match(t)
+        assert_same((off1.cpu().numpy(), pid1.cpu().numpy()), exp, f"single #{round_}")
+        tid, off, pid, per = a.match_batch(flat, offs)
+        assert int(per.sum()) == len(tid)
+        off2 = torch.empty(n, dtype=torch.int64, device="cuda")
+        pid2 = torch.empty(n, dtype=torch.int32, device="cuda")
+        a.match_async(t, off2, pid2, d_count)
+        torch.cuda.synchronize()
+        assert int(d_count.item()) == n
+        assert_same((off2.cpu().numpy(), pid2.cpu().numpy()), exp, f"async #{round_}")
+        assert a.count(t[:0]) == 0
+        assert a.count(t) == n
