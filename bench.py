@@ -170,12 +170,57 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
             "speedup_vs_plain": round(ms_plain / ms_batch, 1)}
 
 
+def bench_served(pf, torch, np, dev) -> dict:
+    """Open-loop Poisson trace (2000 requests at 2000/s, log-uniform 1 KiB..64
+    MiB slices of a pinned 256 MiB pool, four resident byte automata of 500,
+    5000, 20000 and 50000 keywords) through the request server, with
+    continuous batching and with one launch per request in arrival order."""
+    from workloads import config_served
+    t = time.time()
+    w = config_served()
+    pool = torch.empty(len(w.pool), dtype=torch.uint8, pin_memory=True)
+    pool.numpy()[:] = w.pool
+    host = pool.numpy()
+    texts = [host[int(s):int(s) + int(n)] for s, n in zip(w.start, w.length)]
+    arrivals = np.rint(w.arrivals * 1e9).astype(np.int64)
+    automata = [pf.Automaton(k) for k in w.automata]
+    total = int(w.length.sum())
+    log(f"[bench] served: {len(texts)} requests, {total} bytes, automata "
+        f"{[a.info()['n_states'] for a in automata]} states, gen {time.time() - t:.1f}s")
+    out = {"workload": f"{len(texts)} requests, Poisson arrivals at 2000/s, log-uniform 1 KiB..64 MiB slices of a "
+                       "pinned 256 MiB pool (random bytes, plants 1 per 64 KiB per automaton); 4 automata of "
+                       "500/5000/20000/50000 byte keywords |k| 8..64; seed 0",
+           "requests": len(texts), "bytes": total, "offered_gbps": round(total / w.arrivals[-1] / 1e9, 2)}
+    counts = {}
+    for name, mode in (("batched", pf.AC_SERVE_BATCHED), ("fifo", pf.AC_SERVE_FIFO)):
+        with pf.Server(pf.server_opts(mode=mode)) as srv:
+            for a in automata:
+                srv.add_automaton(a)
+            srv.replay([0], [texts[0][:4096]], [0])            # warm-up
+            lat, cnt = srv.replay(w.automaton.astype(np.int32), texts, arrivals)
+            st = srv.stats()
+        span_s = (arrivals[-1] + lat[-1]) * 1e-9
+        counts[name] = cnt
+        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e-6, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
+                     "max_ms": round(float(lat.max()) * 1e-6, 3),
+                     "gbps": round(total / span_s / 1e9, 2),
+                     "batches": int(st["batches"]) - 1, "max_batch_requests": int(st["max_batch_requests"]),
+                     "admission_waits": int(st["admission_waits"]), "rescans": int(st["rescans"])}
+        log(f"[bench] served {name}: p50 {out[name]['p50_ms']} ms, p99 {out[name]['p99_ms']} ms, "
+            f"{out[name]['gbps']} GB/s, {out[name]['batches']} launches")
+    out["same_counts"] = bool((counts["batched"] == counts["fifo"]).all())
+    out["matches"] = int(counts["batched"].sum())
+    out["plain"] = "fifo: one launch per request, one stream, arrival order"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep_1g", choices=["sweep_1g", "large_1g", "tiny", "batched"])
+    ap.add_argument("--workload", default="sweep_1g", choices=["sweep_1g", "large_1g", "tiny", "batched", "served"])
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched (and served) figures added to the single-text line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,6 +259,15 @@ def main() -> int:
             "warmup": args.warmup, "ms_per_step": b["batched_ms"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
             "config": {"workload": "batched: " + b["workload"], "parallelism": "1 GPU"}, "batched": b}), flush=True)
+        return 0
+
+    if args.workload == "served":
+        b = bench_served(pf, torch, np, dev)
+        print(json.dumps({
+            "metric": METRIC, "value": b["batched"]["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": "served: " + b["workload"], "parallelism": "1 GPU"}, "served": b}), flush=True)
         return 0
 
     t = time.time()
@@ -332,6 +386,8 @@ def main() -> int:
         del bufs, host, pinned
         torch.cuda.empty_cache()
         result["batched"] = bench_batched(pf, torch, np, dev, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        result["served"] = bench_served(pf, torch, np, dev)
 
     if not args.no_cpu_baseline:
         from oracle import Oracle

@@ -240,6 +240,10 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *   AC_TABLE_DEPTH      int32[S]           trie depth of each state
  *   AC_TABLE_PREFIX     uint32[2*slots]    {prefix | 1<<31, state | final bit}, 0 = empty
  *   AC_TABLE_TAIL       int32[S]           leaf reached by a forced path, or -1
+ *   AC_TABLE_TAIL_INFO  int32[4*S]         per state: {leaf, keyword-byte position of the
+ *                                          first byte below the state, bytes to the leaf,
+ *                                          the leaf's only keyword id + 1 or 0}; first
+ *                                          field -2 at a leaf, -1 without a forced path
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
  *                              k = 4 + AC_FILTER_* (stride 2, may be empty)
  */
@@ -252,6 +256,7 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
 #define AC_TABLE_DEPTH      7
 #define AC_TABLE_PREFIX     8
 #define AC_TABLE_TAIL       9
+#define AC_TABLE_TAIL_INFO  10
 #define AC_TABLE_FILTER_BASE 100
 
 int ac_compile(const uint8_t *bytes, const int64_t *offsets, int32_t n_patterns,

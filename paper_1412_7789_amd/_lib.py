@@ -13,7 +13,7 @@ AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
 AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19 = 0, 1, 2, 3, 4
 AC_TABLE_CLASS_MAP, AC_TABLE_DENSE, AC_TABLE_NODE, AC_TABLE_LABEL = 1, 2, 3, 4
 AC_TABLE_OUT_OFF, AC_TABLE_OUT_PID, AC_TABLE_DEPTH, AC_TABLE_FILTER_BASE = 5, 6, 7, 100
-AC_TABLE_PREFIX, AC_TABLE_TAIL = 8, 9
+AC_TABLE_PREFIX, AC_TABLE_TAIL, AC_TABLE_TAIL_INFO = 8, 9, 10
 
 # every symbol include/pfac.h declares
 EXPORTS = [

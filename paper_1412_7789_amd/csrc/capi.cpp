@@ -373,6 +373,14 @@ int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const 
 
 int pfac::report_error(int code, const std::string &msg) { return fail(code, msg); }
 
+int pfac::reserve_stream_scratch(hipStream_t stream, int64_t regions) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    CountSlot *slot = nullptr;
+    return count_slot(dev, stream, &slot, regions);
+}
+
 extern "C" {
 
 const char *ac_last_error(void) { return g_err.c_str(); }
@@ -530,6 +538,7 @@ int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_b
         case AC_TABLE_DEPTH: src = P.depth.data(); bytes = int64_t(P.depth.size()) * 4; break;
         case AC_TABLE_PREFIX: src = P.ptab.data(); bytes = int64_t(P.ptab.size()) * 4; break;
         case AC_TABLE_TAIL: src = P.tail.data(); bytes = int64_t(P.tail.size()) * 4; break;
+        case AC_TABLE_TAIL_INFO: src = P.tailinfo.data(); bytes = int64_t(P.tailinfo.size()) * 4; break;
         default:
             if (table > AC_TABLE_FILTER_BASE && table <= AC_TABLE_FILTER_BASE + kNumFilters) {
                 const auto &f = P.filter[table - AC_TABLE_FILTER_BASE - 1];

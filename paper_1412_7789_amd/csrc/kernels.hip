@@ -155,6 +155,25 @@ __device__ __forceinline__ void emit_staged(const DevAut &A, const ScanArgs &S, 
     }
 }
 
+// One keyword id `pid` found at `off` (the caller knows it is the state's only one).
+__device__ __forceinline__ void emit_one(const ScanArgs &S, MatchStage *st, int64_t off, int32_t tid, int32_t pid) {
+    int32_t i = kStageCap;
+    if (st) i = atomicAdd(&st->n, 1);
+    if (i < kStageCap) {
+        st->off[i] = off;
+        st->pid[i] = pid;
+        st->tid[i] = tid;
+    } else {
+        const unsigned long long idx = atomicAdd(S.count, 1ull) - S.count_base;
+        if (idx < static_cast<unsigned long long>(S.cap)) {
+            S.out_off[idx] = off;
+            S.out_pid[idx] = pid;
+            if (S.out_tid) S.out_tid[idx] = tid;
+        }
+    }
+    if (S.per_text) atomicAdd(reinterpret_cast<unsigned long long *>(S.per_text + tid), 1ull);
+}
+
 // Called by every thread of the block once all its walks are done.
 __device__ __forceinline__ void flush_stage(const ScanArgs &S, MatchStage *st) {
     __syncthreads();
@@ -235,6 +254,56 @@ __device__ __forceinline__ void locate_text(const ScanArgs &S, int64_t o, int64_
     }
 }
 
+// 16 bytes from p, of any alignment, assembled from five aligned dword loads.
+// Every dword address is clamped to at most `last` (the aligned dword holding
+// the last readable byte), so no load leaves the buffer; bytes taken from a
+// clamped dword are garbage and must be masked by the caller.
+__device__ __forceinline__ u32x4 load16_clamped(const uint8_t *p, uintptr_t last) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p) & ~uintptr_t(3);
+    const uint32_t sh = uint32_t(reinterpret_cast<uintptr_t>(p) & 3u);
+    uint32_t w[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const uintptr_t ai = a + 4u * uintptr_t(i);
+        w[i] = gload4(reinterpret_cast<const uint8_t *>(ai < last ? ai : last));
+    }
+    u32x4 r;
+    r.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+    r.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+    r.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+    r.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
+    return r;
+}
+
+// XOR of the first n (0..16) bytes of a and b, 0 when they agree.
+__device__ __forceinline__ uint32_t diff16(u32x4 a, u32x4 b, int n) {
+    uint32_t d = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = n - 4 * i;    // bytes of word i that count
+        const uint32_t keep = m >= 4 ? 0xFFFFFFFFu : (m <= 0 ? 0u : (1u << (8 * m)) - 1u);
+        d |= (a[i] ^ b[i]) & keep;
+    }
+    return d;
+}
+
+// Whether text t[0 .. n) equals keyword bytes k[0 .. n) (n <= 64; text[0 ..
+// text_n) is the scanned buffer, which holds t[0 .. n)).  The first 32 bytes
+// of both are loaded in one round trip; longer tails take more.  Keyword
+// bytes may be read up to 67 bytes past a keyword: the keyword section is
+// followed by at least 256 bytes of the same allocation.
+__device__ __forceinline__ bool equal_bytes(const uint8_t *t, const uint8_t *k, int n, const uint8_t *text,
+                                            int64_t text_n) {
+    const uintptr_t tlast = (reinterpret_cast<uintptr_t>(text) + uintptr_t(text_n) - 1u) & ~uintptr_t(3);
+    const uintptr_t klast = ~uintptr_t(0);
+    const u32x4 t0 = load16_clamped(t, tlast), t1 = load16_clamped(t + 16, tlast);
+    const u32x4 k0 = load16_clamped(k, klast), k1 = load16_clamped(k + 16, klast);
+    uint32_t d = diff16(t0, k0, n) | diff16(t1, k1, n - 16);
+    for (int i = 32; d == 0 && i < n; i += 16)
+        d = diff16(load16_clamped(t + i, tlast), load16_clamped(k + i, klast), n - i);
+    return d == 0;
+}
+
 // The rest of the walk from offset o (relative to the scanned buffer) once
 // the exact prefix table gave e = {state at depth K | final bit}: further
 // transitions come from the transition table, and once the remaining path is
@@ -272,20 +341,9 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
             // forced path: bytes d .. d + ti.z of the text against the keyword
             const int64_t L = d + ti.z;
             if (o + L > end) return;
-            int64_t i = d;
-            if (REC) {
-                uint32_t diff = 0;
-                for (; i < L && i < K + 8; ++i) diff |= byte_at(o + i) ^ gload1(A.kw_bytes + ti.y + (i - d));
-                if (diff) return;
-            }
-            for (; i < L; i += 16) {
-                uint32_t diff = 0;
-#pragma unroll
-                for (int u = 0; u < 16; ++u)
-                    if (i + u < L) diff |= gload1(S.text + o + i + u) ^ gload1(A.kw_bytes + ti.y + (i + u - d));
-                if (diff) return;
-            }
-            out(o - tstart, tid, ti.x);
+            if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
+            if (ti.w > 0) emit_one(S, STAGED ? st : nullptr, o - tstart, tid, ti.w - 1);
+            else out(o - tstart, tid, ti.x);
             return;
         }
         if (ti.x == -2) return;        // a leaf: nothing below
@@ -535,18 +593,22 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     // interior chunks, two register sets in turn so that the next chunk's
     // loads are in flight while this one is filtered
     {
+        // The next chunk's loads are issued unconditionally (the last step
+        // reloads its own chunk): with a fixed number of loads between a
+        // chunk's loads and its first use, the compiler waits for that chunk
+        // only, and the loads stay in flight while the current one is filtered.
         ChunkRegs<SEGS> ra, rb;
         int64_t c = F.c_lo + w;
         uint32_t k = 0;
         if (c < F.c_hi) load_interior<SEGS>(F, c, lane, ra);
         while (c < F.c_hi) {
             const int64_t c1 = c + nw;
-            if (c1 < F.c_hi) load_interior<SEGS>(F, c1, lane, rb);
+            load_interior<SEGS>(F, c1 < F.c_hi ? c1 : c, lane, rb);
             push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(ra, lane, sfilt, mul), k++, drain_store);
             c = c1;
             if (c >= F.c_hi) break;
             const int64_t c2 = c + nw;
-            if (c2 < F.c_hi) load_interior<SEGS>(F, c2, lane, ra);
+            load_interior<SEGS>(F, c2 < F.c_hi ? c2 : c, lane, ra);
             push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(rb, lane, sfilt, mul), k++, drain_store);
             c = c2;
         }

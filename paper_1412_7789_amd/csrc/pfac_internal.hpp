@@ -155,5 +155,9 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
 
 // Sets the calling thread's ac_last_error() message; returns `code`.
 int report_error(int code, const std::string &msg);
+
+// Creates the (current device, stream) scratch now, with room for `regions`
+// hit regions, so that later scans on the stream allocate nothing.
+int reserve_stream_scratch(hipStream_t stream, int64_t regions);
 int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t stream, std::string &err);
 }  // namespace pfac

@@ -293,8 +293,9 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
         }
     }
     // per state: {leaf, position in kw_bytes of the first byte below s, bytes
-    // from s down to the leaf, 0} when tail[s] is a deeper leaf; first field
-    // -2 when s is itself a leaf, -1 when the path below s is not forced
+    // from s down to the leaf, leaf's only keyword id + 1 or 0} when tail[s]
+    // is a deeper leaf; first field -2 when s is itself a leaf, -1 when the
+    // path below s is not forced
     P.tailinfo.assign(size_t(S) * 4, 0);
     for (int32_t s = 0; s < S; ++s) {
         const int32_t t = P.tail[size_t(s)];
@@ -304,6 +305,8 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
         ti[0] = t;
         ti[1] = int32_t(offsets[p] - offsets[0]) + P.depth[size_t(s)];
         ti[2] = P.depth[size_t(t)] - P.depth[size_t(s)];
+        // the leaf's keyword id + 1 when exactly one keyword ends there
+        ti[3] = P.out_off[size_t(t) + 1] - P.out_off[size_t(t)] == 1 ? p + 1 : 0;
     }
     // keyword bytes (for tail comparisons) with int32 offsets
     P.kw_bytes.assign(bytes + offsets[0], bytes + offsets[0] + total);

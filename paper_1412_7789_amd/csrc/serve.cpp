@@ -424,6 +424,9 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
     s->o = o;
     hipError_t e = hipGetDevice(&s->device);
     int rc = e == hipSuccess ? AC_OK : report_error(AC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    int cus = 1;
+    if (!rc && (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess)
+        rc = report_error(AC_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
     s->slots.resize(size_t(o.n_streams));
     for (auto &sl : s->slots) {
         if (rc) break;
@@ -433,6 +436,8 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
             break;
         }
         if ((rc = dev_alloc(&sl.d_count, 1)) || (rc = host_alloc(&sl.h_count, 1))) break;
+        // the scan's hit regions for the widest launch (16 waves per CU)
+        if ((rc = pfac::reserve_stream_scratch(sl.stream, int64_t(cus) * 16))) break;
         const int64_t texts = std::min<int64_t>(o.max_batch_texts, 1 << 16);
         rc = grow(sl, std::min<int64_t>(o.max_batch_bytes, int64_t(64) << 20), texts,
                   reserve_matches(o, std::min<int64_t>(o.max_batch_bytes, int64_t(64) << 20)) + 256 * texts);

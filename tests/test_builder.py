@@ -59,6 +59,7 @@ class Tables:
         self.depth = e(L.AC_TABLE_DEPTH, np.int32)
         self.ptab = e(L.AC_TABLE_PREFIX, np.uint32)
         self.tail = e(L.AC_TABLE_TAIL, np.int32)
+        self.tailinfo = e(L.AC_TABLE_TAIL_INFO, np.int32).reshape(-1, 4)
         self.C = self.info["n_classes"]
         self.S = self.info["n_states"]
         self.Sd = self.info["n_dense_states"]
@@ -201,6 +202,20 @@ def test_prefix_table_and_tails(name, kws):
                 break
         leaf = t if (t is not None and not T.children(t)) else None
         assert T.tail[s] == (leaf if leaf is not None else -1), s
+        ti = T.tailinfo[s]
+        if leaf is None:
+            assert ti[0] == -1
+        elif leaf == s:
+            assert ti[0] == -2
+        else:
+            assert ti[0] == leaf and ti[2] == len(path) - 1
+            ids = T.out_pid[T.out_off[leaf]:T.out_off[leaf + 1]]
+            assert ti[3] == (ids[0] + 1 if len(ids) == 1 else 0)
+            # the keyword bytes at ti[1] spell the path below s
+            kw = kws[ids[0]]
+            d = int(T.depth[s])
+            flat = b"".join(kws)
+            assert flat[ti[1]:ti[1] + ti[2]] == kw[d:d + ti[2]]
 
 
 def test_filters_have_no_false_negatives():
