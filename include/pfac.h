@@ -210,9 +210,10 @@ const char *ac_last_error(void);
  * start of the first scan kernel to the end of the last one. */
 float ac_last_scan_ms(void);
 
-/* The same call's split: *stream_ms = the streaming (filter + probe) kernel
- * of the filtered policy or the direct kernel, *walk_ms = the walk kernel
- * (0 for the direct policy); both negative if no timed call was made. */
+/* The same call's split: *stream_ms = the scan kernel (the filtered
+ * policy's streaming kernel, which also walks the candidate offsets it keeps,
+ * or the direct kernel), *walk_ms = time in separate walk kernels (0: the
+ * walks run inside the scan kernel); both negative if no timed call was made. */
 void ac_last_scan_split(float *stream_ms, float *walk_ms);
 
 /* ---- measurement probe -------------------------------------------------------- */

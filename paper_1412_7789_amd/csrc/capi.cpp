@@ -40,7 +40,7 @@ struct CountSlot {
     unsigned long long *d = nullptr;
     unsigned long long *h = nullptr;
     bool stale = false;                        // a failed call may have left *d != *h
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // kernel timing: scan start/stop, walk start/stop
+    hipEvent_t ev[2] = {nullptr, nullptr};   // kernel timing: scan start, stop
     HitScratch hs;                             // hit regions of the filtered policy
 };
 std::mutex g_slots_mu;
@@ -50,15 +50,9 @@ std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;   // entries are never
 int ensure_hits(CountSlot &s, int64_t regions) {
     if (s.hs.regions >= regions) return AC_OK;
     if (s.hs.hits) (void)hipFree(s.hs.hits);
-    if (s.hs.count) (void)hipFree(s.hs.count);
-    if (s.hs.kmin) (void)hipFree(s.hs.kmin);
     s.hs = HitScratch();
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.hs.hits), size_t(regions) * kHitCap * sizeof(uint4));
     if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit regions): ") + hipGetErrorString(e));
-    e = hipMalloc(reinterpret_cast<void **>(&s.hs.count), size_t(regions) * sizeof(int32_t));
-    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit counts): ") + hipGetErrorString(e));
-    e = hipMalloc(reinterpret_cast<void **>(&s.hs.kmin), size_t(regions) * sizeof(uint32_t));
-    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit steps): ") + hipGetErrorString(e));
     s.hs.regions = regions;
     s.hs.cap = kHitCap;
     return AC_OK;
@@ -253,10 +247,6 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     if (timed) {
         T.scan0 = slot->ev[0];
         T.scan1 = slot->ev[1];
-        if (cfg.policy == AC_POLICY_FILTERED) {
-            T.walk0 = slot->ev[2];
-            T.walk1 = slot->ev[3];
-        }
     }
     // a batch clears the word (its per-text counts need a clearing kernel anyway)
     const bool clear = batch || slot->stale;
@@ -275,16 +265,7 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         float ms = -1.0f;
         if ((e = hipEventElapsedTime(&ms, T.scan0, T.scan1)) != hipSuccess) return hip_fail("hipEventElapsedTime", e);
         g_scan_ms = g_stream_ms = ms;
-        if (T.walk0) {
-            float w = -1.0f, all = -1.0f;
-            if ((e = hipEventElapsedTime(&w, T.walk0, T.walk1)) != hipSuccess ||
-                (e = hipEventElapsedTime(&all, T.scan0, T.walk1)) != hipSuccess)
-                return hip_fail("hipEventElapsedTime", e);
-            g_walk_ms = w;
-            g_scan_ms = all;
-        } else {
-            g_walk_ms = 0.0f;
-        }
+        g_walk_ms = 0.0f;
     }
     return int64_t(*slot->h - base);
 }

@@ -39,8 +39,6 @@ namespace {
 
 constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
 constexpr int kDrain = 192;      // candidates taken per drain (3 per lane)
-constexpr int kWalkBlock = 1024;   // threads of a walk-kernel block
-constexpr int kWalkRegions = 16;   // hit regions per walk-kernel block
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
@@ -123,7 +121,7 @@ __device__ __forceinline__ void emit(const DevAut &A, const ScanArgs &S, int64_t
 // Block-level staging of matches in LDS: one global atomic per block instead
 // of one per match.  Matches beyond the stage's capacity go straight out
 // through emit().
-constexpr int kStageCap = 4096;
+constexpr int kStageCap = 3072;   // 48 KiB: fits, with the walk's bookkeeping, in the smallest filter's LDS
 struct MatchStage {
     int64_t off[kStageCap];
     int32_t pid[kStageCap];
@@ -366,8 +364,6 @@ struct FilterLaunch {
     int32_t hit_cap;         // entries per wave region
     uint4 *hits;             // [waves * hit_cap]: {chunk step << 12 | position, prefix-table value,
                              //  the 8 text bytes after the prefix}
-    int32_t *hit_count;      // [waves]
-    uint32_t *hit_kmin;      // [waves]: first chunk step whose hits were not all stored
 };
 
 template <int SEGS>
@@ -615,10 +611,6 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         while (qlen > 0) drain_store(imin(qlen, kDrain));
     }
     kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
-    if (lane == 0) {
-        F.hit_count[w] = hcount;
-        F.hit_kmin[w] = kmin;
-    }
 
     // post-pass 1: interior chunks from the first step that lost a hit
     for (uint32_t k = kmin; kmin != 0xFFFFFFFFu; ++k) {
@@ -648,53 +640,45 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         push(m, 0, drain_walk);
         while (qlen > 0) drain_walk(imin(qlen, kDrain));
     }
-}
 
-// Second kernel of the filtered policy: one wave per hit region of the
-// streaming kernel walks that region's hits (decoding each offset from the
-// streaming launch's chunk order) and emits the matches.
-struct WalkLaunch {
-    const uint4 *hits;
-    const int32_t *hit_count;
-    const uint32_t *hit_kmin;
-    int32_t hit_cap;
-    int64_t regions;        // streaming waves
-    int64_t c_lo, nw;       // first interior chunk, streaming waves (chunk stride)
-    int64_t chunk_bytes, mis;
-};
-
-// Each block takes kWalkRegions consecutive hit regions and spreads their
-// hits over all its threads (one flat index over the regions' counts); the
-// matches found are staged in LDS and leave with one global atomic.
-__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const DevAut A, const ScanArgs S, const WalkLaunch W) {
-    __shared__ __align__(16) uint8_t scls[256];
-    __shared__ MatchStage st;
-    __shared__ int32_t first[kWalkRegions + 1];   // prefix sums of the regions' hit counts
-    const int64_t r0 = int64_t(blockIdx.x) * kWalkRegions;
-    const int nr = int(lmin(kWalkRegions, W.regions - r0));
-    if (threadIdx.x < 64) reinterpret_cast<uint32_t *>(scls)[threadIdx.x] =
-        reinterpret_cast<const uint32_t *>(A.cls)[threadIdx.x];
-    if (threadIdx.x < kWalkRegions) first[threadIdx.x + 1] = int(threadIdx.x) < nr ? W.hit_count[r0 + threadIdx.x] : 0;
-    if (threadIdx.x == 0) {
-        st.n = 0;
-        first[0] = 0;
+    // The block walks the hits its waves stored, spread over all its threads
+    // (one flat index over the waves' regions).  The filter and queues are
+    // no longer needed, so their LDS holds the match stage; the matches leave
+    // with one global atomic per block.
+    // Each wave leaves its hit count and first lost step in its own (empty)
+    // queue; after the barrier the stage, the prefix sums of the counts and
+    // the steps go where the filter was.
+    if (lane == 0) {
+        q[0] = uint32_t(hcount);
+        q[1] = kmin;
     }
     __syncthreads();
-    if (threadIdx.x == 0)
-        for (int j = 0; j < kWalkRegions; ++j) first[j + 1] += first[j];
+    static_assert((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 <= (1u << FLOG2),
+                  "the walk's stage must fit where the filter was");
+    MatchStage *st = reinterpret_cast<MatchStage *>(sfilt);
+    int32_t *wfirst = reinterpret_cast<int32_t *>(sfilt + (sizeof(MatchStage) + 15) / 16 * 16);   // [waves + 1]
+    uint32_t *wkmin = reinterpret_cast<uint32_t *>(wfirst + kMaxWaves + 1);                        // [waves]
+    if (threadIdx.x == 0) {
+        wfirst[0] = 0;
+        for (int j = 0; j < waves_per_block; ++j) {
+            wfirst[j + 1] = wfirst[j] + int32_t(squeue[j * kQueueCap]);
+            wkmin[j] = squeue[j * kQueueCap + 1];
+        }
+        st->n = 0;
+    }
     __syncthreads();
-    const int32_t total = first[kWalkRegions];
+    const int32_t total = wfirst[waves_per_block];
+    const int64_t r0 = int64_t(blockIdx.x) * waves_per_block;
     for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
         int j = 0;
-        while (first[j + 1] <= i) ++j;          // region of flat index i
-        const int64_t region = r0 + j;
-        const uint4 rec = W.hits[region * W.hit_cap + (i - first[j])];
-        if ((rec.x >> 12) >= W.hit_kmin[region]) continue;   // walked by the streaming kernel
-        const int64_t chunk = W.c_lo + region + int64_t(rec.x >> 12) * W.nw;
-        const int64_t o = chunk * W.chunk_bytes + int64_t(rec.x & 4095u) - W.mis;
-        walk_rest<true, true>(A, S, scls, o, rec.y, make_uint2(rec.z, rec.w), &st);
+        while (wfirst[j + 1] <= i) ++j;          // wave (region) of flat index i
+        const uint4 rec = F.hits[(r0 + j) * F.hit_cap + (i - wfirst[j])];
+        if ((rec.x >> 12) >= wkmin[j]) continue;   // walked by that wave's post-pass
+        const int64_t chunk = F.c_lo + r0 + j + int64_t(rec.x >> 12) * nw;
+        const int64_t o = chunk * CH + int64_t(rec.x & 4095u) - F.mis;
+        walk_rest<true, true>(A, S, A.cls, o, rec.y, make_uint2(rec.z, rec.w), st);
     }
-    flush_stage(S, &st);
+    flush_stage(S, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,13 +897,11 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
     if (cfg.policy == AC_POLICY_FILTERED) {
         FilteredGeom G = filtered_geom(a, S.text, S.n, cfg);
         FilterLaunch &F = G.F;
-        if (!hs.hits || !hs.count || !hs.kmin || hs.regions < G.waves || hs.cap <= 0) {
+        if (!hs.hits || hs.regions < G.waves || hs.cap <= 0) {
             err = "scan scratch too small for the launch";
             return AC_EINVAL;
         }
         F.hits = hs.hits;
-        F.hit_count = hs.count;
-        F.hit_kmin = hs.kmin;
         F.hit_cap = hs.cap;
         const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
         // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
@@ -931,20 +913,6 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         e = launch_timed(reinterpret_cast<const void *>(fn), dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), fargs, 0,
                          stream, T.scan0, T.scan1);
         if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
-        WalkLaunch W;
-        W.hits = hs.hits;
-        W.hit_count = hs.count;
-        W.hit_kmin = hs.kmin;
-        W.hit_cap = hs.cap;
-        W.regions = G.waves;
-        W.c_lo = F.c_lo;
-        W.nw = G.waves;
-        W.chunk_bytes = int64_t(cfg.segs) * kSegBytes;
-        W.mis = F.mis;
-        const int64_t wblocks = (G.waves + kWalkRegions - 1) / kWalkRegions;
-        void *wargs[] = {&A, &SA, &W};
-        e = launch_timed(reinterpret_cast<const void *>(walk_kernel), dim3(unsigned(wblocks)), dim3(kWalkBlock), wargs,
-                         0, stream, T.walk0, T.walk1);
     } else if (cfg.policy == AC_POLICY_DIRECT) {
         if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }
         DirectLaunch L;

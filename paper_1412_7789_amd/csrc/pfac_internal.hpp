@@ -132,8 +132,6 @@ uint32_t prefix_hash(uint32_t x, uint32_t mul);
 // Per-stream scratch of the filtered policy: one hit region per streaming wave.
 struct HitScratch {
     uint4 *hits = nullptr;         // [regions * cap]
-    int32_t *count = nullptr;      // [regions]
-    uint32_t *kmin = nullptr;      // [regions]
     int64_t regions = 0;
     int32_t cap = 0;
 };
@@ -141,11 +139,11 @@ constexpr int32_t kHitCap = 1024;
 
 // kernels.hip
 int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
-// Start/stop events of the scan's kernels (each pair may be null): the
-// streaming (or direct) kernel and the walk kernel, taken from their own
-// dispatch packets so that they time the kernel alone.
+// Start/stop events of the scan kernel (the filtered policy's streaming
+// kernel or the direct kernel), taken from its own dispatch packet so that
+// they time the kernel alone; null = untimed.
 struct KernelTiming {
-    hipEvent_t scan0 = nullptr, scan1 = nullptr, walk0 = nullptr, walk1 = nullptr;
+    hipEvent_t scan0 = nullptr, scan1 = nullptr;
 };
 int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg, const HitScratch &hs,
                 hipStream_t stream, std::string &err, const KernelTiming *timing = nullptr);
