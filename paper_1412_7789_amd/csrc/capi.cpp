@@ -37,8 +37,9 @@ int hip_fail(const char *what, hipError_t e) {
 // matches from that value on (ScanArgs::count_base).  The batch calls clear
 // it with their per-text counts.
 struct CountSlot {
-    unsigned long long *d = nullptr;
+    unsigned long long *d = nullptr;           // [0] match count, [1] finished blocks
     unsigned long long *h = nullptr;
+    unsigned long long done_total = 0;         // value of d[1] after the last synchronous call
     bool stale = false;                        // a failed call may have left *d != *h
     hipEvent_t ev[2] = {nullptr, nullptr};   // kernel timing: scan start, stop
     HitScratch hs;                             // hit regions of the filtered policy
@@ -68,9 +69,10 @@ int count_slot(int device, hipStream_t stream, CountSlot **out, int64_t regions)
         return ensure_hits(it->second, regions);
     }
     CountSlot s;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), sizeof(unsigned long long));
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
-    e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocDefault);
+    // coherent: the scan kernel stores the count here itself
+    e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocCoherent);
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
     *s.h = 0;
     s.stale = true;                            // cleared by the first call
@@ -223,15 +225,16 @@ ac_launch resolved(const ac_automaton *a, const ScanArgs &S, const ac_launch *la
 // S.count_base.
 int enqueue(const ac_automaton *a, ScanArgs S, const ac_launch &cfg, bool batch, bool clear,
             unsigned long long *d_count, const HitScratch &hs, hipStream_t stream,
-            const KernelTiming *timing = nullptr) {
+            const KernelTiming *timing = nullptr, int64_t *blocks = nullptr) {
     S.count = d_count;
     std::string err;
     if (clear) {
         S.count_base = 0;
-        int rc = launch_zero(d_count, S.per_text, batch ? S.n_texts : 0, stream, err);
+        S.done_base = 0;
+        int rc = launch_zero(d_count, S.done, S.per_text, batch ? S.n_texts : 0, stream, err);
         if (rc) return fail(rc, err);
     }
-    int rc = launch_scan(a, S, cfg, hs, stream, err, timing);
+    int rc = launch_scan(a, S, cfg, hs, stream, err, timing, blocks);
     return rc ? fail(rc, err) : AC_OK;
 }
 
@@ -254,12 +257,23 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     S.count_base = base;
     if (S.n == 0 && !clear) return 0;              // nothing to scan, nothing to clear
     slot->stale = true;
-    rc = enqueue(a, S, cfg, batch, clear, slot->d, slot->hs, stream, timed ? &T : nullptr);
+    // the filtered policy's last block stores the count into the pinned word
+    const bool reported = cfg.policy == AC_POLICY_FILTERED && S.n > 0;
+    S.done = slot->d + 1;                          // cleared with the count
+    if (clear) slot->done_total = 0;
+    S.done_base = slot->done_total;
+    S.host_count = reported ? slot->h : nullptr;
+    int64_t blocks = 0;
+    rc = enqueue(a, S, cfg, batch, clear, slot->d, slot->hs, stream, timed ? &T : nullptr, &blocks);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(slot->h, slot->d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
+    hipError_t e = hipSuccess;
+    if (!reported) {
+        e = hipMemcpyAsync(slot->h, slot->d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
+    }
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    if (reported) slot->done_total += uint64_t(blocks);
     slot->stale = false;
     if (timed) {
         float ms = -1.0f;

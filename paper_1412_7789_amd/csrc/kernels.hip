@@ -679,6 +679,18 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         walk_rest<true, true>(A, S, A.cls, o, rec.y, make_uint2(rec.z, rec.w), st);
     }
     flush_stage(S, st);
+
+    // The last block to finish hands the count to the host.
+    if (S.host_count && threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long t = atomicAdd(S.done, 1ull);
+        if (t == S.done_base + gridDim.x - 1) {
+            __threadfence();
+            const unsigned long long c = atomicAdd(S.count, 0ull);
+            *(__attribute__((address_space(1))) unsigned long long *)(S.host_count) = c;
+            __threadfence_system();
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -720,9 +732,10 @@ __global__ __launch_bounds__(1024) void direct_kernel(const DevAut A, const Scan
     }
 }
 
-__global__ void zero_kernel(unsigned long long *count, int64_t *per_text, int32_t n_texts) {
+__global__ void zero_kernel(unsigned long long *count, unsigned long long *done, int64_t *per_text, int32_t n_texts) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i == 0) *count = 0ull;
+    if (i == 0 && done) *done = 0ull;
     if (per_text && i < n_texts) per_text[i] = 0;
 }
 
@@ -872,11 +885,11 @@ int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t 
     return AC_OK;
 }
 
-int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts, hipStream_t stream,
-                std::string &err) {
+int launch_zero(unsigned long long *count, unsigned long long *done, int64_t *per_text, int32_t n_texts,
+                hipStream_t stream, std::string &err) {
     const int32_t threads = 256;
     const int32_t blocks = std::max<int32_t>(1, (std::max<int32_t>(n_texts, 1) + threads - 1) / threads);
-    zero_kernel<<<blocks, threads, 0, stream>>>(count, per_text, n_texts);
+    zero_kernel<<<blocks, threads, 0, stream>>>(count, done, per_text, n_texts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { err = std::string("zero_kernel launch: ") + hipGetErrorString(e); return AC_EHIP; }
     return AC_OK;
@@ -888,7 +901,8 @@ int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, cons
 }
 
 int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err, const KernelTiming *timing) {
+                hipStream_t stream, std::string &err, const KernelTiming *timing, int64_t *blocks) {
+    if (blocks) *blocks = 0;
     const KernelTiming none;
     const KernelTiming &T = timing ? *timing : none;
     if (S.n <= 0) return AC_OK;
@@ -912,6 +926,7 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
         void *fargs[] = {&A, &SA, &F};
         e = launch_timed(reinterpret_cast<const void *>(fn), dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), fargs, 0,
                          stream, T.scan0, T.scan1);
+        if (blocks && e == hipSuccess) *blocks = G.grid;
         if (e != hipSuccess) { err = std::string("scan launch: ") + hipGetErrorString(e); return AC_EHIP; }
     } else if (cfg.policy == AC_POLICY_DIRECT) {
         if (S.text_off) { err = "direct policy does not scan batches"; return AC_ENOTSUP; }

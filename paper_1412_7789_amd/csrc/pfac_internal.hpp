@@ -105,6 +105,12 @@ struct ScanArgs {
     unsigned long long *count;
     unsigned long long count_base; // value of *count before this scan: match i goes to index i - base
     int64_t *per_text;             // batch only, may be null
+    // Optional report of the count to the host: the streaming kernel's last
+    // block to finish (*done reaching done_base + blocks) stores *count into
+    // host_count, a pinned host word.  host_count == nullptr: no report.
+    unsigned long long *done;
+    unsigned long long done_base;
+    unsigned long long *host_count;
 };
 
 }  // namespace pfac
@@ -145,9 +151,12 @@ int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, cons
 struct KernelTiming {
     hipEvent_t scan0 = nullptr, scan1 = nullptr;
 };
+// *blocks (if given) receives the number of blocks of the scan kernel (0
+// when nothing was launched).
 int launch_scan(const ac_automaton *a, const ScanArgs &args, const ac_launch &cfg, const HitScratch &hs,
-                hipStream_t stream, std::string &err, const KernelTiming *timing = nullptr);
-int launch_zero(unsigned long long *count, int64_t *per_text, int32_t n_texts,
+                hipStream_t stream, std::string &err, const KernelTiming *timing = nullptr,
+                int64_t *blocks = nullptr);
+int launch_zero(unsigned long long *count, unsigned long long *done, int64_t *per_text, int32_t n_texts,
                 hipStream_t stream, std::string &err);
 void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &cfg);
 
