@@ -104,10 +104,13 @@ typedef struct {
     int32_t table_in_lds;   /* DIRECT: -1/0 = auto, 1 = force LDS, 2 = global     */
     int32_t flags;          /* AC_LAUNCH_* bits                                   */
     int32_t stride;         /* FILTERED: 1 = test every offset's prefix; 2 = test
-                             * odd offsets against the keywords' 3-byte windows at
-                             * positions 0 and 1 (needs every keyword >= 4 bytes),
-                             * each positive test making both offsets of its pair
-                             * candidates; 0 = auto                              */
+                             * every second offset against the keywords' 3-byte
+                             * windows at positions 0 and 1 (needs every keyword
+                             * >= 4 bytes), a positive test making the offset and
+                             * the one before it candidates; 4 = every fourth
+                             * offset against the windows at positions 0 .. 3
+                             * (keywords >= 6 bytes), a positive making it and the
+                             * three before it candidates; 0 = auto              */
     int32_t reserved[4];
 } ac_launch;
 
@@ -195,7 +198,8 @@ typedef struct {
     double build_ms;         /* host build + upload time                        */
     int64_t prefix_table_bytes;  /* exact prefix -> state table                 */
     int64_t tail_bytes;      /* forced-path leaves + keyword bytes               */
-    int32_t reserved[4];
+    int32_t n_windows4;      /* distinct 3-byte windows at positions 0 .. 3 (0 = stride 4 unavailable) */
+    int32_t reserved[3];
 } ac_info_t;
 
 int ac_info(const ac_automaton *a, ac_info_t *out);
@@ -246,7 +250,8 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                                          the leaf's only keyword id + 1 or 0}; first
  *                                          field -2 at a leaf, -1 without a forced path
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
- *                              k = 4 + AC_FILTER_* (stride 2, may be empty)
+ *                              k = 4 + AC_FILTER_* (stride 2, may be empty),
+ *                              k = 8 + AC_FILTER_* (stride 4, may be empty)
  */
 #define AC_TABLE_CLASS_MAP  1
 #define AC_TABLE_DENSE      2

@@ -178,6 +178,7 @@ void fill_info(const Plan &P, ac_info_t *o) {
     o->dense_depth = P.dense_depth;
     o->n_prefixes = P.n_prefixes;
     o->n_windows2 = P.sampled ? P.n_windows2 : 0;
+    o->n_windows4 = P.sampled4 ? P.n_windows4 : 0;
     o->dense_bytes = int64_t(P.dense.size()) * 4;
     o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
     o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;
@@ -200,7 +201,7 @@ int check_launch(const ac_launch *l) {
         return fail(AC_EINVAL, "ac_launch: segs must be 1, 2 or 4");
     if (l->grid_per_cu < 0 || l->grid_per_cu > 64) return fail(AC_EINVAL, "ac_launch: bad grid_per_cu");
     if (l->flags & ~AC_LAUNCH_TIME_SCAN) return fail(AC_EINVAL, "ac_launch: unknown flags");
-    if (l->stride < 0 || l->stride > 2) return fail(AC_EINVAL, "ac_launch: stride must be 0, 1 or 2");
+    if (l->stride < 0 || l->stride > 4 || l->stride == 3) return fail(AC_EINVAL, "ac_launch: stride must be 0, 1, 2 or 4");
     return AC_OK;
 }
 

@@ -432,8 +432,9 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
             else v = sfilt[p >> shift];
             mj |= v << s;
         }
-        // stride 2: a window tested at odd s covers the offset pair (s - 1, s)
+        // a window tested at s covers the offsets s - STRIDE + 1 .. s
         if (STRIDE == 2) mj |= mj >> 1;
+        if (STRIDE == 4) mj |= (mj >> 1) | (mj >> 2) | (mj >> 3);
         mseg[j] = mj;
     }
     // bit 16 j + s: segment j, byte s
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         for (int i = threadIdx.x; i < (2 << A.ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
     }
     {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[(STRIDE - 1) * kNumFilterKinds + F.filter_kind - 1]);
+        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[stride_set(STRIDE) * kNumFilterKinds + F.filter_kind - 1]);
         uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
         for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
     }
@@ -773,8 +774,9 @@ FilteredFn pick_filter(int kind, int segs) {
     }
 }
 
-// stride 2 exists for K = 3 only
+// strides 2 and 4 exist for K = 3 only
 FilteredFn pick_filtered(int K, int kind, int segs, int stride) {
+    if (stride == 4) return pick_filter<3, 4>(kind, segs);
     if (stride == 2) return pick_filter<3, 2>(kind, segs);
     if (K == 1) return pick_filter<1, 1>(kind, segs);
     if (K == 2) return pick_filter<2, 1>(kind, segs);
@@ -836,16 +838,19 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
     if (cfg.policy == AC_POLICY_AUTO) cfg.policy = AC_POLICY_FILTERED;
     if (batch) cfg.policy = AC_POLICY_FILTERED;
     if (cfg.policy == AC_POLICY_FILTERED) {
-        // Stride 2 halves the filter work but doubles the keys in the filter;
-        // it pays while the 2^20-bit map stays sparse (measured on MI355X:
-        // 1000 printable keywords 0.34 vs 0.40 ms per GiB; 20000 byte
-        // keywords 0.78 vs 0.68 ms).
-        const bool sampled_ok = P.sampled && P.n_windows2 <= 8192;
-        if (cfg.stride != 1 && cfg.stride != 2) cfg.stride = sampled_ok ? 2 : 1;
+        // A stride of 2 or 4 cuts the filter work by that factor but puts 2
+        // or 4 windows per keyword in the filter, and a positive test makes 2
+        // or 4 candidates.  Measured on MI355X (ms per GiB): 1000 printable
+        // keywords 0.31 at stride 1, 0.26 at stride 2, 0.28 at stride 4;
+        // 20000 byte keywords 0.49 at stride 1, 0.59 at stride 2.  Stride 4
+        // is used only when asked for.
+        const bool s2_ok = P.sampled && P.n_windows2 <= 8192;
+        if (cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4) cfg.stride = s2_ok ? 2 : 1;
+        if (cfg.stride == 4 && !P.sampled4) cfg.stride = P.sampled ? 2 : 1;
         if (cfg.stride == 2 && !P.sampled) cfg.stride = 1;
         if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_BITS19) {
             // keys in the filter: prefixes (stride 1) or windows (stride 2)
-            const int64_t keys = cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;
+            const int64_t keys = cfg.stride == 4 ? P.n_windows4 : cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;
             const bool small_text = len < (int64_t(16) << 20);
             const bool many = keys > 1500;
             if (small_text) cfg.filter = many ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;

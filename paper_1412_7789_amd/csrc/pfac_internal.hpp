@@ -41,7 +41,9 @@ constexpr int kNumFilterKinds = 4;
 // Filter sets: [0, 4) test every offset against the keywords' K-byte
 // prefixes; [4, 8) test odd offsets against the 3-byte windows at keyword
 // positions 0 and 1 (built when K = 3 and every keyword has >= 4 bytes).
-constexpr int kNumFilters = 2 * kNumFilterKinds;
+constexpr int kNumFilters = 3 * kNumFilterKinds;   // strides 1, 2 and 4
+// Filter set of a sampling stride: 0 (stride 1), 1 (stride 2), 2 (stride 4).
+constexpr int stride_set(int stride) { return stride == 4 ? 2 : stride - 1; }
 
 // Host-side build result (the "plan").  States are numbered breadth first,
 // so the children of a state are contiguous and sorted by byte, and every
@@ -63,7 +65,9 @@ struct Plan {
     int32_t n_prefixes = 0;
     int32_t n_windows2 = 0;        // distinct 3-byte windows at keyword positions 0 and 1
     bool sampled = false;          // the stride-2 filters exist
-    std::vector<uint8_t> filter[kNumFilters];   // indexed by (stride - 1) * 4 + kind - 1
+    int32_t n_windows4 = 0;        // distinct 3-byte windows at keyword positions 0 .. 3
+    bool sampled4 = false;         // the stride-4 filters exist
+    std::vector<uint8_t> filter[kNumFilters];   // indexed by stride_set(stride) * 4 + kind - 1
     int32_t ptab_bits = 0;
     std::vector<uint32_t> ptab;    // [2 << ptab_bits]: {prefix | valid, state | final}
     std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1

@@ -207,26 +207,33 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
     std::sort(prefixes.begin(), prefixes.end());
     prefixes.erase(std::unique(prefixes.begin(), prefixes.end()), prefixes.end());
     P.n_prefixes = int32_t(prefixes.size());
-    // windows for the stride-2 filters: bytes [0, 3) and [1, 4) of each keyword
-    std::vector<uint32_t> windows;
-    P.sampled = P.K == 3 && P.min_len >= 4;
-    if (P.sampled) {
-        windows.reserve(size_t(n) * 2);
+    // windows for the sampled filters: bytes [j, j + 3) of each keyword for
+    // j < 2 (stride 2, keywords of 4 bytes or more) and j < 4 (stride 4, 6
+    // bytes or more)
+    auto windows_of = [&](int count) {
+        std::vector<uint32_t> w;
+        w.reserve(size_t(n) * size_t(count));
         for (int32_t p = 0; p < n; ++p) {
             const uint8_t *k = kw(p);
-            windows.push_back(uint32_t(k[0]) | uint32_t(k[1]) << 8 | uint32_t(k[2]) << 16);
-            windows.push_back(uint32_t(k[1]) | uint32_t(k[2]) << 8 | uint32_t(k[3]) << 16);
+            for (int j = 0; j < count; ++j)
+                w.push_back(uint32_t(k[j]) | uint32_t(k[j + 1]) << 8 | uint32_t(k[j + 2]) << 16);
         }
-        std::sort(windows.begin(), windows.end());
-        windows.erase(std::unique(windows.begin(), windows.end()), windows.end());
-    }
+        std::sort(w.begin(), w.end());
+        w.erase(std::unique(w.begin(), w.end()), w.end());
+        return w;
+    };
+    P.sampled = P.K == 3 && P.min_len >= 4;
+    P.sampled4 = P.K == 3 && P.min_len >= 6;
+    const std::vector<uint32_t> windows = P.sampled ? windows_of(2) : std::vector<uint32_t>();
+    const std::vector<uint32_t> windows4 = P.sampled4 ? windows_of(4) : std::vector<uint32_t>();
     P.n_windows2 = int32_t(windows.size());
-    for (int set = 0; set < 2; ++set) {
-        const std::vector<uint32_t> &keys = set == 0 ? prefixes : windows;
+    P.n_windows4 = int32_t(windows4.size());
+    for (int set = 0; set < 3; ++set) {
+        const std::vector<uint32_t> &keys = set == 0 ? prefixes : set == 1 ? windows : windows4;
         for (int kind = 1; kind <= kNumFilterKinds; ++kind) {
             FilterGeom g = filter_geom(kind);
             std::vector<uint8_t> &f = P.filter[set * kNumFilterKinds + kind - 1];
-            if (set == 1 && !P.sampled) { f.clear(); continue; }
+            if ((set == 1 && !P.sampled) || (set == 2 && !P.sampled4)) { f.clear(); continue; }
             f.assign(size_t(g.bytes), 0);
             for (uint32_t x : keys) {
                 uint32_t h = prefix_hash(x, mul);

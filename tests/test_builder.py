@@ -219,20 +219,38 @@ def test_prefix_table_and_tails(name, kws):
 
 
 def test_filters_have_no_false_negatives():
+    """Every key of each filter set is present in every map of that set:
+    K-byte prefixes (stride 1), windows [0,3) and [1,4) (stride 2) and
+    windows [0,3) .. [3,6) (stride 4)."""
     kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
     T = Tables(kws)
     K = T.info["prefix_len"]
+    assert K == 3
     geoms = {1: (False, 17), 2: (True, 17), 3: (False, 16), 4: (True, 16)}
-    for kind, (bitmap, flog2) in geoms.items():
-        f = T.plan.export(L.AC_TABLE_FILTER_BASE + kind, np.uint8)
-        assert len(f) == 1 << flog2
-        for k in kws:
-            h = T.plan.hash(int.from_bytes(k[:K], "little"))
-            if bitmap:
-                w = f.view(np.uint32)[h >> (32 - (flog2 - 2))]
-                assert (int(w) >> (h & 31)) & 1
-            else:
-                assert f[h >> (32 - flog2)] == 1
+    key_sets = {0: {k[:K] for k in kws},
+                1: {k[j:j + 3] for k in kws for j in range(2)},
+                2: {k[j:j + 3] for k in kws for j in range(4)}}
+    assert T.info["n_windows2"] == len(key_sets[1])
+    assert T.info["n_windows4"] == len(key_sets[2])
+    for set_, keys in key_sets.items():
+        for kind, (bitmap, flog2) in geoms.items():
+            f = T.plan.export(L.AC_TABLE_FILTER_BASE + 4 * set_ + kind, np.uint8)
+            assert len(f) == 1 << flog2
+            for key in keys:
+                h = T.plan.hash(int.from_bytes(key, "little"))
+                if bitmap:
+                    w = f.view(np.uint32)[h >> (32 - (flog2 - 2))]
+                    assert (int(w) >> (h & 31)) & 1
+                else:
+                    assert f[h >> (32 - flog2)] == 1
+
+
+def test_sampled_filters_need_long_enough_keywords():
+    T = Tables([b"abcde", b"bcdefg"])          # shortest 5: stride 2 only
+    assert T.info["n_windows2"] > 0 and T.info["n_windows4"] == 0
+    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 9, np.uint8)) == 0
+    T = Tables([b"abc", b"abcdef"])            # shortest 3: neither
+    assert T.info["n_windows2"] == 0 and T.info["n_windows4"] == 0
 
 
 def test_build_errors(lib):

@@ -53,6 +53,7 @@ POLICIES = [
     ("stride1-bytes17-s4", dict(policy=1, filter=1, segs=4, stride=1)),
     ("stride2-bits20-s4", dict(policy=1, filter=2, segs=4, stride=2)),
     ("stride2-bytes16-s1-b256", dict(policy=1, filter=3, segs=1, stride=2, block=256)),
+    ("stride4-falls-back", dict(policy=1, filter=2, segs=4, stride=4)),
     ("direct-lds", dict(policy=2, table_in_lds=1)),
     ("direct-global", dict(policy=2, table_in_lds=2)),
 ]
@@ -114,11 +115,12 @@ def test_every_single_byte_keyword():
                     oracle_match(kws, text), f"single bytes {name}")
 
 
-def test_plants_straddling_chunk_boundaries():
+@pytest.mark.parametrize("lens,strides", [((4, 7, 12, 31, 64), (1, 2)), ((6, 7, 12, 31, 64), (4,))])
+def test_plants_straddling_chunk_boundaries(lens, strides):
     """Keywords planted across every position near 1 KiB / 2 KiB / 4 KiB
-    boundaries, for each chunk geometry."""
+    boundaries, for each chunk geometry and sampling stride."""
     rng = np.random.default_rng(5)
-    kws = [bytes(rng.integers(97, 123, size=L, dtype=np.uint8)) for L in (4, 7, 12, 31, 64)]
+    kws = [bytes(rng.integers(97, 123, size=L, dtype=np.uint8)) for L in lens]
     text = rng.integers(97, 123, size=3 * 4096 + 100, dtype=np.uint8)
     texts = []
     for boundary in (1024, 2048, 4096, 8192):
@@ -130,7 +132,7 @@ def test_plants_straddling_chunk_boundaries():
                     t[o:o + len(k)] = np.frombuffer(k, dtype=np.uint8)
                     texts.append(t)
     a = pf.Automaton(kws)
-    for segs, stride in ((1, 1), (2, 2), (4, 1), (4, 2)):
+    for segs, stride in [(sg, st) for sg in (1, 2, 4) for st in strides]:
         cfg = pf.launch_config(policy=1, segs=segs, stride=stride)
         for i, t in enumerate(texts):
             if i % 16 == 0:
@@ -164,13 +166,13 @@ def test_errors_are_reported():
         a.count(t, launch=pf.launch_config(block=100))
 
 
-@pytest.mark.parametrize("stride", [1, 2])
+@pytest.mark.parametrize("stride", [1, 2, 4])
 def test_hit_region_overflow(stride):
     """A periodic text where a third of all offsets match fills every wave's
     hit region many times over, so the streaming kernel's post-pass walks the
-    chunks whose hits were dropped (and the walk kernel skips their stored
+    chunks whose hits were dropped (and the final walk skips their stored
     records)."""
-    kws = [b"abcab", b"cabca", b"zzzz"]
+    kws = [b"abcab", b"cabca", b"zzzz"] if stride < 4 else [b"abcabc", b"cabcab", b"zzzzzz"]
     text = np.frombuffer(b"abc" * (16 << 20 // 3), dtype=np.uint8)
     text = np.ascontiguousarray(text[: 16 << 20])
     say("overflow", stride, len(text))
@@ -204,3 +206,19 @@ def test_interleaved_call_kinds_share_a_stream():
         assert_same((off2.cpu().numpy(), pid2.cpu().numpy()), exp, f"async #{round_}")
         assert a.count(t[:0]) == 0
         assert a.count(t) == n
+
+
+@pytest.mark.parametrize("offset", [0, 1, 2, 3, 5])
+def test_stride4_unaligned_and_ragged(offset):
+    """Stride-4 sampling (keywords of 8..32 bytes) on every alignment and on
+    lengths around chunk and segment sizes."""
+    from workloads import config_sweep
+    w = config_sweep(300_000)
+    a = pf.Automaton(w.keywords)
+    for n in [0, 5, 6, 7, 8, 15, 16, 17, 1023, 1024, 1031, 4096, 4099, 16384 + 9, 65536 + 3, 300_000]:
+        text = w.text[:n]
+        for segs in (1, 4):
+            cfg = pf.launch_config(policy=1, segs=segs, stride=4)
+            say("stride4", offset, n, segs)
+            assert_same(gpu_match(w.keywords, text, launch=cfg, offset=offset, automaton=a),
+                        oracle_match(w.keywords, text), f"offset {offset} n {n} segs {segs}")
