@@ -243,7 +243,10 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *   AC_TABLE_OUT_OFF    int32[S+1]         CSR offsets into AC_TABLE_OUT_PID
  *   AC_TABLE_OUT_PID    int32[...]         keyword ids ending at each state
  *   AC_TABLE_DEPTH      int32[S]           trie depth of each state
- *   AC_TABLE_PREFIX     uint32[2*slots]    {prefix | 1<<31, state | final bit}, 0 = empty
+ *   AC_TABLE_PREFIX     uint32[2*slots]    buckets of 4 {key, value} slots: key = prefix |
+ *                                          next byte << 24, value = state | has-next 1<<30 |
+ *                                          final 1<<31 (0 = empty slot); a prefix lies in
+ *                                          one of the two buckets ac_plan_prefix_buckets gives
  *   AC_TABLE_TAIL       int32[S]           leaf reached by a forced path, or -1
  *   AC_TABLE_TAIL_INFO  int32[4*S]         per state: {leaf, keyword-byte position of the
  *                                          first byte below the state, bytes to the leaf,
@@ -271,6 +274,8 @@ int ac_plan_info(const ac_plan *p, ac_info_t *out);
 int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_bytes);
 /* Filter hash of a prefix value x (prefix bytes little-endian), as the kernel computes it. */
 uint32_t ac_plan_hash(const ac_plan *p, uint32_t x);
+/* The two buckets (of 4 slots) of the exact prefix table that may hold prefix x. */
+void ac_plan_prefix_buckets(const ac_plan *p, uint32_t x, uint32_t *b1, uint32_t *b2);
 void ac_plan_free(ac_plan *p);
 
 #ifdef __cplusplus

@@ -20,7 +20,7 @@ EXPORTS = [
     "ac_build", "ac_build_csr", "ac_free", "ac_match", "ac_match_ex", "ac_match_async",
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
-    "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read",
+    "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
 ]
 # every symbol include/pfac_serve.h declares
 SERVE_EXPORTS = [
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_plan_info": (ctypes.c_int, [vp, vp]),
         "ac_plan_export": (i64, [vp, i32, vp, i64]),
         "ac_plan_hash": (u32, [vp, u32]),
+        "ac_plan_prefix_buckets": (None, [vp, u32, vp, vp]),
         "ac_plan_free": (None, [vp]),
         "ac_last_scan_ms": (ctypes.c_float, []),
         "ac_last_scan_split": (None, [vp, vp]),

@@ -91,6 +91,11 @@ class Plan:
     def hash(self, x: int) -> int:
         return int(L.load().ac_plan_hash(self._h, x & 0xFFFFFFFF))
 
+    def prefix_buckets(self, x: int) -> Tuple[int, int]:
+        b1, b2 = ctypes.c_uint32(), ctypes.c_uint32()
+        L.load().ac_plan_prefix_buckets(self._h, x & 0xFFFFFFFF, ctypes.byref(b1), ctypes.byref(b2))
+        return b1.value, b2.value
+
     def close(self) -> None:
         if self._h:
             L.load().ac_plan_free(self._h)

@@ -556,6 +556,11 @@ uint32_t ac_plan_hash(const ac_plan *p, uint32_t x) {
     return prefix_hash(x & kmask, p->p.hash_mul);
 }
 
+void ac_plan_prefix_buckets(const ac_plan *p, uint32_t x, uint32_t *b1, uint32_t *b2) {
+    if (!p || !b1 || !b2) return;
+    prefix_buckets(x & 0xFFFFFFu, p->p.hash_mul, p->p.ptab_bits, *b1, *b2);
+}
+
 void ac_plan_free(ac_plan *p) { delete p; }
 
 }  // extern "C"

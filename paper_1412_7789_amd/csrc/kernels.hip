@@ -215,20 +215,27 @@ __device__ __forceinline__ uint32_t hash24(uint32_t x, uint32_t mul) {
 // Exact prefix lookup for the K-byte prefix x: returns {key, value} of its
 // slot -- key = x | next byte << 24, value = state at depth K | has-next bit
 // 30 | final bit 31 -- or value 0 when no keyword starts with x.  The table
-// is at most half full, so the linear probe always meets an empty slot.
+// holds buckets of four {key, value} slots and x lies in one of its two
+// buckets, so both are read at once and no further probing is needed.
 constexpr uint32_t kHasNext = 0x40000000u;
 constexpr uint32_t kStateMask = 0x3fffffffu;
 
-template <typename Load>
-__device__ __forceinline__ uint2 prefix_state(Load load, int bits, uint32_t x, uint32_t mul) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t slot = (hash24(x, mul) >> (32 - bits)) & mask;
-    while (true) {
-        const uint2 kv = load(slot);
-        if (kv.y == 0u) return kv;
-        if ((kv.x & 0xFFFFFFu) == x) return kv;
-        slot = (slot + 1u) & mask;
+template <typename LoadBucket>
+__device__ __forceinline__ uint2 prefix_state(LoadBucket load, int bits, uint32_t x, uint32_t mul) {
+    const int nb = bits - 2;
+    const uint32_t b1 = hash24(x, mul) >> (32 - nb);
+    uint32_t b2 = hash24(x, kPrefixMul2) >> (32 - nb);
+    if (b2 == b1) b2 = b1 ^ 1u;
+    u32x4 q[4];
+    load(b1, q[0], q[1]);
+    load(b2, q[2], q[3]);
+    uint2 r = make_uint2(0u, 0u);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (q[i].y != 0u && (q[i].x & 0xFFFFFFu) == x) r = make_uint2(q[i].x, q[i].y);
+        if (q[i].w != 0u && (q[i].z & 0xFFFFFFu) == x) r = make_uint2(q[i].z, q[i].w);
     }
+    return r;
 }
 
 // Text of a candidate offset: [start, end) of the text holding o and its id.
@@ -490,11 +497,14 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     int qlen = 0;
 
     auto probe = [&](uint32_t x) __attribute__((always_inline)) -> uint2 {
-        if (pt_lds) return prefix_state([&](uint32_t i) { return make_uint2(sptab[2 * i], sptab[2 * i + 1]); },
-                                        A.ptab_bits, x, mul);
-        return prefix_state([&](uint32_t i) {
-            return make_uint2(gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i)),
-                              gload4(reinterpret_cast<const uint8_t *>(A.ptab + 2 * i + 1)));
+        if (pt_lds)
+            return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
+                lo = reinterpret_cast<const u32x4 *>(sptab)[2 * b];
+                hi = reinterpret_cast<const u32x4 *>(sptab)[2 * b + 1];
+            }, A.ptab_bits, x, mul);
+        return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
+            lo = gload16(reinterpret_cast<const uint8_t *>(A.ptab + 8 * b));
+            hi = gload16(reinterpret_cast<const uint8_t *>(A.ptab + 8 * b + 4));
         }, A.ptab_bits, x, mul);
     };
     auto offset_of = [&](uint32_t ent) __attribute__((always_inline)) {

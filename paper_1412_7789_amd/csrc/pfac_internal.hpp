@@ -16,6 +16,7 @@ constexpr int kWave = 64;
 constexpr int kSegBytes = 1024;          // bytes one wave loads per segment (64 lanes x 16 B)
 constexpr int kMaxPrefix = 3;            // bytes hashed by the candidate filter
 constexpr uint32_t kDefaultHashMul = 0x9E3779u;   // odd 24-bit multiplier
+constexpr uint32_t kPrefixMul2 = 0x5BD1E5u;       // second bucket of the prefix table
 constexpr int64_t kDefaultDenseBudget = 64ll << 20;
 constexpr int32_t kFinalBit = int32_t(0x80000000u);
 
@@ -69,7 +70,7 @@ struct Plan {
     bool sampled4 = false;         // the stride-4 filters exist
     std::vector<uint8_t> filter[kNumFilters];   // indexed by stride_set(stride) * 4 + kind - 1
     int32_t ptab_bits = 0;
-    std::vector<uint32_t> ptab;    // [2 << ptab_bits]: {prefix | valid, state | final}
+    std::vector<uint32_t> ptab;    // [2 << ptab_bits]: buckets of 4 {key, value} slots
     std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1
     std::vector<int32_t> tailinfo; // [4 S]: {leaf or -1, kw_bytes position, remaining bytes, 0}
     std::vector<uint8_t> kw_bytes; // keywords back to back
@@ -139,6 +140,8 @@ namespace pfac {
 int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
                  const ac_build_opts *opts, Plan &out, std::string &err);
 uint32_t prefix_hash(uint32_t x, uint32_t mul);
+// The two candidate buckets (of 4 slots) of prefix x in a table of 2^bits slots.
+void prefix_buckets(uint32_t x, uint32_t mul, int bits, uint32_t &b1, uint32_t &b2);
 // Per-stream scratch of the filtered policy: one hit region per streaming wave.
 struct HitScratch {
     uint4 *hits = nullptr;         // [regions * cap]

@@ -32,6 +32,59 @@ uint32_t prefix_hash(uint32_t x, uint32_t mul) {
     return uint32_t(uint64_t(x & 0xFFFFFFu) * uint64_t(mul & 0xFFFFFFu));
 }
 
+void prefix_buckets(uint32_t x, uint32_t mul, int bits, uint32_t &b1, uint32_t &b2) {
+    const int nb = bits - 2;                      // buckets of 4 slots
+    b1 = prefix_hash(x, mul) >> (32 - nb);
+    b2 = prefix_hash(x, kPrefixMul2) >> (32 - nb);
+    if (b2 == b1) b2 = b1 ^ 1u;
+}
+
+namespace {
+
+// Places every (key, value) in one of its two buckets by cuckoo insertion
+// (a deterministic walk of evictions); false when some key found no place.
+bool build_cuckoo(const std::vector<std::pair<uint32_t, uint32_t>> &items, int bits, uint32_t mul,
+                  std::vector<uint32_t> &table) {
+    table.assign(size_t(2) << bits, 0u);
+    uint32_t rng = 0x2545F491u;
+    for (auto item : items) {
+        uint32_t key = item.first, val = item.second;
+        uint32_t b1, b2;
+        prefix_buckets(key & 0xFFFFFFu, mul, bits, b1, b2);
+        uint32_t next = b1;
+        bool placed = false;
+        for (int kick = 0; kick < 1000 && !placed; ++kick) {
+            // a free slot in either bucket ends the walk
+            for (uint32_t b : {b1, b2}) {
+                for (uint32_t j = 0; j < 4 && !placed; ++j) {
+                    const size_t at = (size_t(b) * 4 + j) * 2;
+                    if (table[at + 1] == 0u) {
+                        table[at] = key;
+                        table[at + 1] = val;
+                        placed = true;
+                    }
+                }
+                if (placed) break;
+            }
+            if (placed) break;
+            // evict a slot of `next` and carry its entry to its other bucket
+            rng ^= rng << 13; rng ^= rng >> 17; rng ^= rng << 5;
+            const size_t at = (size_t(next) * 4 + (rng & 3u)) * 2;
+            std::swap(key, table[at]);
+            std::swap(val, table[at + 1]);
+            uint32_t e1, e2;
+            prefix_buckets(key & 0xFFFFFFu, mul, bits, e1, e2);
+            b1 = e1;
+            b2 = e2;
+            next = (e1 == next) ? e2 : e1;
+        }
+        if (!placed) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
 int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
                  const ac_build_opts *opts, Plan &P, std::string &err) {
     auto t0 = std::chrono::steady_clock::now();
@@ -248,40 +301,44 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
     }
 
     // ---- exact prefix table: K-byte prefix -> state at depth K ------------
-    // Open addressing with linear probing, at most half full, probed from
-    // the same product as the filters.  Slot = {key, value}:
+    // Two-choice cuckoo table of 2^bits slots in buckets of 4, at most half
+    // full: every prefix lies in one of its two buckets, so a lookup reads
+    // two buckets and never probes further.  Slot = {key, value}:
     //   key   = prefix (24 bits) | next byte << 24
     //   value = state | has-next << 30 | final << 31, 0 for an empty slot.
     // When the state has exactly one child, "next byte" is that child's edge
     // byte and has-next is set: an offset whose following byte differs
     // cannot match deeper than the prefix.
     {
-        int bits = 6;
-        while ((int64_t(1) << bits) < 2 * int64_t(P.n_prefixes)) ++bits;
-        P.ptab_bits = bits;
-        const uint32_t mask = (1u << bits) - 1u;
-        P.ptab.assign(size_t(2) << bits, 0u);
+        std::vector<std::pair<uint32_t, uint32_t>> items;   // (key, value), one per prefix
+        items.reserve(size_t(P.n_prefixes));
+        std::vector<uint32_t> seen;
         for (int32_t p = 0; p < n; ++p) {
             uint32_t x = 0;
             for (int j = 0; j < P.K; ++j) x |= uint32_t(kw(p)[j]) << (8 * j);
+            seen.push_back(x);
+        }
+        std::sort(seen.begin(), seen.end());
+        seen.erase(std::unique(seen.begin(), seen.end()), seen.end());
+        for (uint32_t x : seen) {
             int32_t s = 0;   // follow the trie for K bytes
             for (int j = 0; j < P.K; ++j) {
-                const uint8_t b = kw(p)[j];
+                const uint8_t b = uint8_t(x >> (8 * j));
                 int32_t lo = P.first_child[size_t(s)], hi = lo + P.n_child[size_t(s)];
                 while (lo < hi && P.label[size_t(lo)] != b) ++lo;
                 s = lo;
             }
-            uint32_t slot = prefix_hash(x, mul) >> (32 - bits);
-            while (P.ptab[size_t(slot) * 2 + 1] != 0u && (P.ptab[size_t(slot) * 2] & 0xFFFFFFu) != x)
-                slot = (slot + 1u) & mask;
             uint32_t key = x, val = uint32_t(s) | (is_final(s) ? 0x80000000u : 0u);
             if (P.n_child[size_t(s)] == 1) {
                 key |= uint32_t(P.label[size_t(P.first_child[size_t(s)])]) << 24;
                 val |= 0x40000000u;
             }
-            P.ptab[size_t(slot) * 2] = key;
-            P.ptab[size_t(slot) * 2 + 1] = val;
+            items.emplace_back(key, val);
         }
+        int bits = 6;
+        while ((int64_t(1) << bits) < 2 * int64_t(P.n_prefixes)) ++bits;
+        while (!build_cuckoo(items, bits, mul, P.ptab)) ++bits;
+        P.ptab_bits = bits;
     }
 
     // ---- unary tails: state -> leaf when the rest of the path is forced -----

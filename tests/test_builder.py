@@ -158,15 +158,21 @@ def test_prefix_table_and_tails(name, kws):
             s = nxt[0]
         return s
 
+    slots = len(T.ptab) // 2
+    assert slots & (slots - 1) == 0 and 2 * T.info["n_prefixes"] <= slots
+    occupied = [(int(T.ptab[2 * i]), int(T.ptab[2 * i + 1])) for i in range(slots) if T.ptab[2 * i + 1]]
+    assert len(occupied) == T.info["n_prefixes"]          # each prefix stored once
+
     def lookup(x):
-        """(key, value) of x's slot; value 0 when absent."""
-        bits = int(np.log2(len(T.ptab) // 2))
-        slot = T.plan.hash(x) >> (32 - bits)
-        while True:
-            k, v = int(T.ptab[2 * slot]), int(T.ptab[2 * slot + 1])
-            if v == 0 or (k & 0xFFFFFF) == x:
-                return k, v
-            slot = (slot + 1) % (len(T.ptab) // 2)
+        """(key, value) of x's slot in its two buckets; value 0 when absent."""
+        b1, b2 = T.plan.prefix_buckets(x)
+        assert b1 != b2 and max(b1, b2) < slots // 4
+        for b in (b1, b2):
+            for j in range(4):
+                k, v = int(T.ptab[2 * (4 * b + j)]), int(T.ptab[2 * (4 * b + j) + 1])
+                if v and (k & 0xFFFFFF) == x:
+                    return k, v
+        return 0, 0
 
     keyset = set(kws)
     pref = {k[:K] for k in kws}
