@@ -68,6 +68,9 @@ __device__ __forceinline__ unsigned long long readlane64(unsigned long long v, i
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// Third descriptor word of a raw (untyped, unswizzled) buffer on gfx9-family GPUs.
+constexpr int kBufferFlags = 0x00020000;
+
 // Loads through an explicit global-address-space pointer: pointers taken out
 // of a by-value struct otherwise lower to flat loads, which also occupy the
 // LDS counter and would serialise with the filter lookups.
@@ -379,17 +382,21 @@ struct ChunkRegs {
     uint32_t tail;   // first dword after the chunk (halo of the last lane)
 };
 
-// Interior chunk: one coalesced 16-byte load per lane and segment.
+// Interior chunk: one coalesced 16-byte load per lane and segment, as buffer
+// loads from a descriptor based at the chunk (uniform, in SGPRs) with
+// per-lane offsets that never change, so issuing the next chunk's loads
+// needs no address register that an earlier load might still be writing.
 template <int SEGS>
 __device__ __forceinline__ void load_interior(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
-    const uint8_t *p = F.base + c * CH + lane * 16;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(F.base + c * CH), short(0), int(CH + 16), kBufferFlags);
 #pragma unroll
     for (int j = 0; j < SEGS; ++j) {
-        const u32x4 q = gload16(p + j * kSegBytes);
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(lane * 16u + uint32_t(j) * kSegBytes), 0, 0);
         R.d[j][0] = q.x; R.d[j][1] = q.y; R.d[j][2] = q.z; R.d[j][3] = q.w;
     }
-    R.tail = gload4(F.base + (c + 1) * CH);
+    R.tail = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(CH), 0, 0);
 }
 
 // Chunk that overlaps either end of the text: bytes outside it read as 0.
