@@ -3,22 +3,30 @@
 
 Default workload: 1000 printable-ASCII keywords (|k| in 8..32) and 1 GiB of
 printable text with one planted keyword per 4 KiB.  One step is one call of
-the matcher over the whole text, inputs already in HBM: scan kernel, match
-emission and the synchronous return of the exact count.
+the matcher over the whole text, inputs already in HBM: the scan kernel
+(filter, prefix probe and walks in one launch), match emission and the
+synchronous return of the exact count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Prints ONE JSON line: text GB/s (1 GB = 1e9 B), the roofline of the
-dominant kernel (the streaming filter kernel: text bytes read / its HIP-event
-time, against the 8 TB/s HBM peak), the achievable read bandwidth of the same
-buffer measured by a streaming-read probe, and the CPU oracle timed on a
-bounded sample.
+Prints ONE JSON line: text GB/s (1 GB = 1e9 B); the roofline of the scan
+kernel (text read + matches written per launch / its duration from HIP
+events, against the 8 TB/s HBM peak; HBM traffic from the stored rocprofv3
+counters while the device code is unchanged); the achievable read bandwidth
+of the same buffer from a streaming-read probe; the CPU oracle timed on a
+bounded sample; and, for the default workload, the batched (4096 texts) and
+served (request trace at 1x and 4x the arrival rate) figures against their
+plain forms.
+
+    python bench.py --workload batched | served | crossover | large_1g | tiny
+
+gives one of those alone; ``crossover`` times the paper's own experiment
+(GPU end-to-end against the serial CPU matcher over the paper's text sizes).
 
     python bench.py --copy-calibration
 
-instead times a plain device-to-device copy of 1 GiB (the reference kernel
-for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters) and prints its
-bytes per call.
+instead runs a plain device-to-device copy of 1 GiB (the reference kernel
+for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE counters).
 """
 
 from __future__ import annotations
@@ -170,7 +178,7 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
             "speedup_vs_plain": round(ms_plain / ms_batch, 1)}
 
 
-def bench_served(pf, torch, np, dev) -> dict:
+def bench_served(pf, torch, np, dev, rate_scale: float = 1.0) -> dict:
     """Open-loop Poisson trace (2000 requests at 2000/s, log-uniform 1 KiB..64
     MiB slices of a pinned 256 MiB pool, four resident byte automata of 500,
     5000, 20000 and 50000 keywords) through the request server, with
@@ -182,21 +190,25 @@ def bench_served(pf, torch, np, dev) -> dict:
     pool.numpy()[:] = w.pool
     host = pool.numpy()
     texts = [host[int(s):int(s) + int(n)] for s, n in zip(w.start, w.length)]
-    arrivals = np.rint(w.arrivals * 1e9).astype(np.int64)
+    arrivals = np.rint(w.arrivals / rate_scale * 1e9).astype(np.int64)
     automata = [pf.Automaton(k) for k in w.automata]
     total = int(w.length.sum())
     log(f"[bench] served: {len(texts)} requests, {total} bytes, automata "
         f"{[a.info()['n_states'] for a in automata]} states, gen {time.time() - t:.1f}s")
-    out = {"workload": f"{len(texts)} requests, Poisson arrivals at 2000/s, log-uniform 1 KiB..64 MiB slices of a "
+    out = {"workload": f"{len(texts)} requests, Poisson arrivals at {2000 * rate_scale:.0f}/s, log-uniform 1 KiB..64 MiB slices of a "
                        "pinned 256 MiB pool (random bytes, plants 1 per 64 KiB per automaton); 4 automata of "
                        "500/5000/20000/50000 byte keywords |k| 8..64; seed 0",
-           "requests": len(texts), "bytes": total, "offered_gbps": round(total / w.arrivals[-1] / 1e9, 2)}
+           "requests": len(texts), "bytes": total, "offered_gbps": round(total * rate_scale / w.arrivals[-1] / 1e9, 2)}
     counts = {}
     for name, mode in (("batched", pf.AC_SERVE_BATCHED), ("fifo", pf.AC_SERVE_FIFO)):
         with pf.Server(pf.server_opts(mode=mode)) as srv:
             for a in automata:
                 srv.add_automaton(a)
-            srv.replay([0], [texts[0][:4096]], [0])            # warm-up
+            # warm-up: every automaton at a small and a large size, so that each
+            # kernel variant is loaded and every stream's buffers exist
+            warm = [(a, t) for a in range(len(automata)) for t in (host[:4096], host[:32 << 20])]
+            srv.replay([a for a, _ in warm], [t for _, t in warm], [0] * len(warm))
+            warm_batches = srv.stats()["batches"]
             lat, cnt = srv.replay(w.automaton.astype(np.int32), texts, arrivals)
             st = srv.stats()
         span_s = (arrivals[-1] + lat[-1]) * 1e-9
@@ -205,7 +217,7 @@ def bench_served(pf, torch, np, dev) -> dict:
                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
                      "max_ms": round(float(lat.max()) * 1e-6, 3),
                      "gbps": round(total / span_s / 1e9, 2),
-                     "batches": int(st["batches"]) - 1, "max_batch_requests": int(st["max_batch_requests"]),
+                     "batches": int(st["batches"]) - int(warm_batches), "max_batch_requests": int(st["max_batch_requests"]),
                      "admission_waits": int(st["admission_waits"]), "rescans": int(st["rescans"])}
         log(f"[bench] served {name}: p50 {out[name]['p50_ms']} ms, p99 {out[name]['p99_ms']} ms, "
             f"{out[name]['gbps']} GB/s, {out[name]['batches']} launches")
@@ -215,12 +227,70 @@ def bench_served(pf, torch, np, dev) -> dict:
     return out
 
 
+def bench_crossover(pf, torch, np, dev, reps: int = 7) -> dict:
+    """The paper's question (Section IV): from what text size does the GPU
+    beat the serial CPU matcher?  Paper workload (permutations of a..z over
+    131-byte alphabet lines) at the paper's sizes, k x 16375 B and k x 1310 B
+    for k = 1..41.  GPU end-to-end = pinned host->device copy of the text +
+    synchronous match + copy of the matches back; CPU = the oracle's serial
+    match phase (its CPU-baseline role), one thread."""
+    from oracle import Oracle
+    from workloads import paper_workload
+    out = {"gpu": "pinned H2D + ac_match_ex (sync) + D2H of matches, median of %d" % reps,
+           "cpu": "oracle serial Aho-Corasick match phase, 1 thread, median of %d" % reps}
+    for n_pat in (5, 10):
+        for step_lines, label in ((125, "fig6"), (10, "fig7")):
+            w = paper_workload(n_pat, step_lines * 41)
+            a = pf.Automaton(w.keywords)
+            o = Oracle(w.keywords)
+            host = torch.from_numpy(w.text).pin_memory()
+            d_text = torch.empty(len(w.text), dtype=torch.uint8, device=dev)
+            d_off = torch.empty(len(w.text) // 20 + 64, dtype=torch.int64, device=dev)
+            d_pid = torch.empty_like(d_off, dtype=torch.int32)
+            h_off = torch.empty(d_off.numel(), dtype=torch.int64).pin_memory()
+            h_pid = torch.empty(d_off.numel(), dtype=torch.int32).pin_memory()
+            cfg = pf.launch_config(flags=pf.AC_LAUNCH_TIME_SCAN)
+            sizes, gpu_ms, kern_ms, cpu_ms = [], [], [], []
+            for k in range(1, 42):
+                n = 131 * step_lines * k
+                tg, tk, tc = [], [], []
+                for r in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    d_text[:n].copy_(host[:n], non_blocking=True)
+                    cnt = a.match_into(d_text[:n], d_off, d_pid, launch=cfg)
+                    h_off[:cnt].copy_(d_off[:cnt], non_blocking=True)
+                    h_pid[:cnt].copy_(d_pid[:cnt], non_blocking=True)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    tk.append(pf.last_scan_ms())
+                    c0 = time.perf_counter()
+                    eo, _ = o.match(w.text[:n])
+                    c1 = time.perf_counter()
+                    assert len(eo) == cnt
+                    if r:                                   # first round warms up
+                        tg.append((t1 - t0) * 1e3)
+                        tc.append((c1 - c0) * 1e3)
+                sizes.append(n)
+                gpu_ms.append(round(float(np.median(tg)), 4))
+                kern_ms.append(round(float(np.median(tk[1:])), 4))
+                cpu_ms.append(round(float(np.median(tc)), 4))
+            o.close()
+            cross = next((n for n, g, c in zip(sizes, gpu_ms, cpu_ms) if g < c), None)
+            key = f"{label}_{n_pat}_patterns"
+            out[key] = {"bytes": sizes, "gpu_end_to_end_ms": gpu_ms, "gpu_kernel_ms": kern_ms,
+                        "cpu_ms": cpu_ms, "crossover_bytes": cross}
+            log(f"[bench] crossover {key}: GPU end-to-end beats the CPU from {cross} bytes "
+                f"(GPU {gpu_ms[0]:.3f}..{gpu_ms[-1]:.3f} ms, CPU {cpu_ms[0]:.3f}..{cpu_ms[-1]:.3f} ms)")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="sweep_1g", choices=["sweep_1g", "large_1g", "tiny", "batched", "served"])
+    ap.add_argument("--workload", default="sweep_1g", choices=["sweep_1g", "large_1g", "tiny", "batched", "served", "crossover"])
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched (and served) figures added to the single-text line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -261,13 +331,24 @@ def main() -> int:
             "config": {"workload": "batched: " + b["workload"], "parallelism": "1 GPU"}, "batched": b}), flush=True)
         return 0
 
+    if args.workload == "crossover":
+        b = bench_crossover(pf, torch, np, dev)
+        print(json.dumps({"metric": "text size from which the GPU beats the serial CPU matcher (paper workload)",
+                          "value": b["fig6_5_patterns"]["crossover_bytes"], "unit": "bytes", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "u8", "data": "synthetic",
+                          "config": {"workload": "paper: permutations of a..z over 131-byte alphabet lines"},
+                          "cpu_baseline_crossover": b}), flush=True)
+        return 0
+
     if args.workload == "served":
         b = bench_served(pf, torch, np, dev)
+        b4 = bench_served(pf, torch, np, dev, rate_scale=4.0)
         print(json.dumps({
             "metric": METRIC, "value": b["batched"]["gbps"], "unit": "GB/s", "n_gpus": 1, "steps": 1,
             "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-            "config": {"workload": "served: " + b["workload"], "parallelism": "1 GPU"}, "served": b}), flush=True)
+            "config": {"workload": "served: " + b["workload"], "parallelism": "1 GPU"}, "served": b,
+            "served_x4_rate": b4}), flush=True)
         return 0
 
     t = time.time()
@@ -314,15 +395,15 @@ def main() -> int:
     # reading the events back costs the host ~35 us per call.
     times = [timed_step(i) for i in range(args.steps)]
     torch.cuda.synchronize()
-    scan_ms, stream_ms, walk_ms = (float(np.mean([t[i] for t in times])) for i in range(3))
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, kernels {scan_ms:.3f} ms "
-        f"(streaming {stream_ms:.3f} + walk {walk_ms:.3f}), {count} matches")
+    scan_ms, stream_ms = (float(np.mean([t[i] for t in times])) for i in range(2))
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, scan kernel {scan_ms:.3f} ms, {count} matches")
 
-    # roofline of the dominant kernel (streaming filter kernel): it reads the
-    # text once; the matches (12 B each) are written by the walk kernel
+    # roofline of the dominant kernel: the filtered policy's one kernel reads
+    # the text once and writes the matches (12 B each); its hit records are
+    # internal scratch, not algorithmic traffic
     filtered = launch["policy"] == 1
     kernel_ms = stream_ms if filtered else scan_ms
-    alg_bytes = n if filtered else n + 12 * count
+    alg_bytes = n + 12 * count
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     traffic = stored_traffic(args.workload)
 
@@ -370,7 +451,6 @@ def main() -> int:
                      "kernel_ms": round(kernel_ms, 4),
                      "kernel_timing": f"HIP events from the kernels' dispatch packets, mean of {args.steps} "
                                       "steps run right after the timed region",
-                     "walk_kernel_ms": round(walk_ms, 4) if filtered else None,
                      "all_kernels_ms": round(scan_ms, 4),
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "achievable_read_gbps": round(probe_gbps, 1),
@@ -388,6 +468,7 @@ def main() -> int:
         result["batched"] = bench_batched(pf, torch, np, dev, args.steps, args.warmup)
         torch.cuda.empty_cache()
         result["served"] = bench_served(pf, torch, np, dev)
+        result["served_x4_rate"] = bench_served(pf, torch, np, dev, rate_scale=4.0)
 
     if not args.no_cpu_baseline:
         from oracle import Oracle

@@ -438,9 +438,10 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
         if ((rc = dev_alloc(&sl.d_count, 1)) || (rc = host_alloc(&sl.h_count, 1))) break;
         // the scan's hit regions for the widest launch (16 waves per CU)
         if ((rc = pfac::reserve_stream_scratch(sl.stream, int64_t(cus) * 16))) break;
+        // sized for a full batch, so that serving never reallocates (a single
+        // request longer than max_batch_bytes still grows its stream's buffers)
         const int64_t texts = std::min<int64_t>(o.max_batch_texts, 1 << 16);
-        rc = grow(sl, std::min<int64_t>(o.max_batch_bytes, int64_t(64) << 20), texts,
-                  reserve_matches(o, std::min<int64_t>(o.max_batch_bytes, int64_t(64) << 20)) + 256 * texts);
+        rc = grow(sl, o.max_batch_bytes, texts, reserve_matches(o, o.max_batch_bytes) + 256 * texts);
     }
     if (rc) {
         for (auto &sl : s->slots) release_slot(sl);
