@@ -94,6 +94,8 @@ typedef struct {
 #define AC_FILTER_BITS20    2  /* 2^20-bit map, 128 KiB of LDS                  */
 #define AC_FILTER_BYTES16   3  /* 2^16-entry byte map, 64 KiB of LDS            */
 #define AC_FILTER_BITS19    4  /* 2^19-bit map, 64 KiB of LDS                   */
+#define AC_FILTER_DUAL19    5  /* two 2^19-bit maps with independent hashes,   */
+                               /* 128 KiB of LDS; both bits must be set         */
 
 typedef struct {
     int32_t policy;         /* AC_POLICY_*                                        */
@@ -253,8 +255,10 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                                          the leaf's only keyword id + 1 or 0}; first
  *                                          field -2 at a leaf, -1 without a forced path
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
- *                              k = 4 + AC_FILTER_* (stride 2, may be empty),
- *                              k = 8 + AC_FILTER_* (stride 4, may be empty)
+ *                              k = 5 + AC_FILTER_* (stride 2, may be empty),
+ *                              k = 10 + AC_FILTER_* (stride 4, may be empty);
+ *                              AC_FILTER_DUAL19: map A (first 64 KiB, hashed as
+ *                              ac_plan_hash) then map B (ac_plan_hash2)
  */
 #define AC_TABLE_CLASS_MAP  1
 #define AC_TABLE_DENSE      2
@@ -274,6 +278,8 @@ int ac_plan_info(const ac_plan *p, ac_info_t *out);
 int64_t ac_plan_export(const ac_plan *p, int32_t table, void *dst, int64_t dst_bytes);
 /* Filter hash of a prefix value x (prefix bytes little-endian), as the kernel computes it. */
 uint32_t ac_plan_hash(const ac_plan *p, uint32_t x);
+/* The second filter hash (map B of AC_FILTER_DUAL19). */
+uint32_t ac_plan_hash2(const ac_plan *p, uint32_t x);
 /* The two buckets (of 4 slots) of the exact prefix table that may hold prefix x. */
 void ac_plan_prefix_buckets(const ac_plan *p, uint32_t x, uint32_t *b1, uint32_t *b2);
 void ac_plan_free(ac_plan *p);

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libpfac.so")
 AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_ENOTSUP = 0, -1, -2, -3, -4
 AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
 AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19 = 0, 1, 2, 3, 4
+AC_FILTER_DUAL19 = 5
 AC_TABLE_CLASS_MAP, AC_TABLE_DENSE, AC_TABLE_NODE, AC_TABLE_LABEL = 1, 2, 3, 4
 AC_TABLE_OUT_OFF, AC_TABLE_OUT_PID, AC_TABLE_DEPTH, AC_TABLE_FILTER_BASE = 5, 6, 7, 100
 AC_TABLE_PREFIX, AC_TABLE_TAIL, AC_TABLE_TAIL_INFO = 8, 9, 10
@@ -21,6 +22,7 @@ EXPORTS = [
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
+    "ac_plan_hash2",
 ]
 # every symbol include/pfac_serve.h declares
 SERVE_EXPORTS = [
@@ -127,6 +129,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_plan_info": (ctypes.c_int, [vp, vp]),
         "ac_plan_export": (i64, [vp, i32, vp, i64]),
         "ac_plan_hash": (u32, [vp, u32]),
+        "ac_plan_hash2": (u32, [vp, u32]),
         "ac_plan_prefix_buckets": (None, [vp, u32, vp, vp]),
         "ac_plan_free": (None, [vp]),
         "ac_last_scan_ms": (ctypes.c_float, []),

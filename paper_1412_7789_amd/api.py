@@ -91,6 +91,9 @@ class Plan:
     def hash(self, x: int) -> int:
         return int(L.load().ac_plan_hash(self._h, x & 0xFFFFFFFF))
 
+    def hash2(self, x: int) -> int:
+        return int(L.load().ac_plan_hash2(self._h, x & 0xFFFFFFFF))
+
     def prefix_buckets(self, x: int) -> Tuple[int, int]:
         b1, b2 = ctypes.c_uint32(), ctypes.c_uint32()
         L.load().ac_plan_prefix_buckets(self._h, x & 0xFFFFFFFF, ctypes.byref(b1), ctypes.byref(b2))

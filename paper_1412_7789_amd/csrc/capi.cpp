@@ -194,7 +194,7 @@ void fill_info(const Plan &P, ac_info_t *o) {
 int check_launch(const ac_launch *l) {
     if (!l) return AC_OK;
     if (l->policy < AC_POLICY_AUTO || l->policy > AC_POLICY_DIRECT) return fail(AC_EINVAL, "ac_launch: bad policy");
-    if (l->filter < AC_FILTER_AUTO || l->filter > AC_FILTER_BITS19) return fail(AC_EINVAL, "ac_launch: bad filter");
+    if (l->filter < AC_FILTER_AUTO || l->filter > AC_FILTER_DUAL19) return fail(AC_EINVAL, "ac_launch: bad filter");
     if (l->block != 0 && l->block != 256 && l->block != 512 && l->block != 1024)
         return fail(AC_EINVAL, "ac_launch: block must be 256, 512 or 1024");
     if (l->segs != 0 && l->segs != 1 && l->segs != 2 && l->segs != 4)
@@ -554,6 +554,12 @@ uint32_t ac_plan_hash(const ac_plan *p, uint32_t x) {
     if (!p) return 0;
     const uint32_t kmask = p->p.K >= 3 ? 0xFFFFFFu : ((1u << (8 * p->p.K)) - 1u);
     return prefix_hash(x & kmask, p->p.hash_mul);
+}
+
+uint32_t ac_plan_hash2(const ac_plan *p, uint32_t x) {
+    if (!p) return 0;
+    const uint32_t kmask = p->p.K >= 3 ? 0xFFFFFFu : ((1u << (8 * p->p.K)) - 1u);
+    return prefix_hash(x & kmask, kFilterMul2);
 }
 
 void ac_plan_prefix_buckets(const ac_plan *p, uint32_t x, uint32_t *b1, uint32_t *b2) {

@@ -419,7 +419,7 @@ __device__ __forceinline__ void load_partial(const FilterLaunch &F, int64_t c, u
 // Candidate mask of one chunk: bit 16 j + s is set when the K bytes at offset
 // s of the lane's 16 bytes in segment j hash to a set filter entry (stride
 // 1), or when the 3 bytes at the odd offset of s's pair do (stride 2).
-template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE>
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL>
 __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
                                                            const uint8_t *sfilt, uint32_t mul) {
     constexpr uint32_t kmask = K >= 3 ? 0xFFFFFFu : ((1u << (8 * K)) - 1u);
@@ -442,8 +442,17 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
             if (K < 3) x &= kmask;
             const uint32_t p = hash24(x, mul);
             uint32_t v;
-            if (BITMAP) v = __builtin_amdgcn_ubfe(reinterpret_cast<const uint32_t *>(sfilt)[p >> shift], p, 1u);
-            else v = sfilt[p >> shift];
+            if (DUAL) {
+                // two maps of 2^(FLOG2 - 3) words, independent hashes: both bits must be set
+                const uint32_t p2 = hash24(x, kFilterMul2);
+                const uint32_t *fm = reinterpret_cast<const uint32_t *>(sfilt);
+                v = __builtin_amdgcn_ubfe(fm[p >> (shift + 1)], p, 1u) &
+                    __builtin_amdgcn_ubfe(fm[(1u << (FLOG2 - 3)) + (p2 >> (shift + 1))], p2, 1u);
+            } else if (BITMAP) {
+                v = __builtin_amdgcn_ubfe(reinterpret_cast<const uint32_t *>(sfilt)[p >> shift], p, 1u);
+            } else {
+                v = sfilt[p >> shift];
+            }
             mj |= v << s;
         }
         // a window tested at s covers the offsets s - STRIDE + 1 .. s
@@ -460,14 +469,15 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
 // Streaming kernel of the filtered policy.  Candidate offsets wait in a
 // per-wave LDS queue; a drain takes kDrain of them at once (each lane loads
 // the prefix window of kDrain / 64 candidates with independent loads, then
-// probes the exact prefix table) and appends the surviving prefixes, with the
-// 8 text bytes after them, to the wave's hit region with plain stores.  The
-// streaming loop has no walk, atomic, call or other dependent global access;
-// walk_kernel finishes the stored hits.  Hits that do not fit the region are
-// not stored: the region records the first chunk step that lost one, and a
-// post-pass after the loop re-filters the wave's chunks from that step on
-// (and the partial chunks at the text's ends) and walks their hits itself.
-template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE>
+// looks the prefix up in the exact prefix table) and appends the surviving
+// prefixes, with the 8 text bytes after them, to the wave's hit region with
+// plain stores.  The chunk loop has no walk, atomic, call or other dependent
+// global access.  Hits that do not fit the region are not stored: the region
+// records the first chunk step that lost one, and a post-pass after the loop
+// re-filters the wave's chunks from that step on (and the partial chunks at
+// the text's ends) and walks their hits itself.  Finally the block walks the
+// stored hits of its waves.
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL>
 __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
@@ -618,12 +628,12 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         while (c < F.c_hi) {
             const int64_t c1 = c + nw;
             load_interior<SEGS>(F, c1 < F.c_hi ? c1 : c, lane, rb);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(ra, lane, sfilt, mul), k++, drain_store);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(ra, lane, sfilt, mul), k++, drain_store);
             c = c1;
             if (c >= F.c_hi) break;
             const int64_t c2 = c + nw;
             load_interior<SEGS>(F, c2 < F.c_hi ? c2 : c, lane, ra);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(rb, lane, sfilt, mul), k++, drain_store);
+            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(rb, lane, sfilt, mul), k++, drain_store);
             c = c2;
         }
         while (qlen > 0) drain_store(imin(qlen, kDrain));
@@ -636,7 +646,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         if (c >= F.c_hi) break;
         ChunkRegs<SEGS> r;
         load_interior<SEGS>(F, c, lane, r);
-        push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(r, lane, sfilt, mul), k, drain_walk);
+        push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(r, lane, sfilt, mul), k, drain_walk);
         while (qlen > 0) drain_walk(imin(qlen, kDrain));
     }
     // post-pass 2: chunks overlapping an end of the text: [0, p0) and [p1, n_chunks)
@@ -647,7 +657,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         const int64_t pc = i < p0 ? i : p1 + (i - p0);
         ChunkRegs<SEGS> r;
         load_partial<SEGS>(F, pc, lane, r);
-        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE>(r, lane, sfilt, mul);
+        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(r, lane, sfilt, mul);
         for (int b = 0; b < SEGS * 16; ++b) {
             // keep offsets o with 0 <= o and o + K <= n
             const int64_t o = pc * CH + (b >> 4) * kSegBytes + int64_t(lane) * 16 + (b & 15) - F.mis;
@@ -772,12 +782,12 @@ __global__ __launch_bounds__(256) void probe_read_kernel(const uint8_t *buf, int
 
 using FilteredFn = void (*)(const DevAut, const ScanArgs, const FilterLaunch);
 
-template <int K, bool BM, int FLOG2, int STRIDE>
+template <int K, bool BM, int FLOG2, int STRIDE, bool DUAL = false>
 FilteredFn pick_segs(int segs) {
     switch (segs) {
-        case 1: return filtered_kernel<K, BM, 1, FLOG2, STRIDE>;
-        case 2: return filtered_kernel<K, BM, 2, FLOG2, STRIDE>;
-        default: return filtered_kernel<K, BM, 4, FLOG2, STRIDE>;
+        case 1: return filtered_kernel<K, BM, 1, FLOG2, STRIDE, DUAL>;
+        case 2: return filtered_kernel<K, BM, 2, FLOG2, STRIDE, DUAL>;
+        default: return filtered_kernel<K, BM, 4, FLOG2, STRIDE, DUAL>;
     }
 }
 
@@ -787,6 +797,7 @@ FilteredFn pick_filter(int kind, int segs) {
         case AC_FILTER_BYTES17: return pick_segs<K, false, 17, STRIDE>(segs);
         case AC_FILTER_BITS20: return pick_segs<K, true, 17, STRIDE>(segs);
         case AC_FILTER_BYTES16: return pick_segs<K, false, 16, STRIDE>(segs);
+        case AC_FILTER_DUAL19: return pick_segs<K, true, 17, STRIDE, true>(segs);
         default: return pick_segs<K, true, 16, STRIDE>(segs);
     }
 }
@@ -855,34 +866,45 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
     if (cfg.policy == AC_POLICY_AUTO) cfg.policy = AC_POLICY_FILTERED;
     if (batch) cfg.policy = AC_POLICY_FILTERED;
     if (cfg.policy == AC_POLICY_FILTERED) {
-        // A stride of 2 or 4 cuts the filter work by that factor but puts 2
-        // or 4 windows per keyword in the filter, and a positive test makes 2
-        // or 4 candidates.  Measured on MI355X (ms per GiB): 1000 printable
-        // keywords 0.31 at stride 1, 0.26 at stride 2, 0.28 at stride 4;
-        // 20000 byte keywords 0.49 at stride 1, 0.59 at stride 2.  Stride 4
-        // is used only when asked for.
-        const bool s2_ok = P.sampled && P.n_windows2 <= 8192;
-        if (cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4) cfg.stride = s2_ok ? 2 : 1;
+        // Sampling stride and map, chosen by the number of keys the map must
+        // hold.  A stride of 2 halves the probes but holds two windows per
+        // keyword and makes two candidates per positive; the dual map spends a
+        // second hash and LDS read per probe to square the false-positive
+        // rate.  Measured on MI355X (ms per GiB): 1000 printable keywords
+        // (2000 windows) 0.26 with one 2^20-bit map at stride 2, 0.30 dual,
+        // 0.32 at stride 1; 20000 byte keywords (28000 windows) 0.31 dual at
+        // stride 2, 0.44 one map at stride 1, 0.48 dual at stride 1, 0.56 one
+        // map at stride 2.  Stride 4 is used only when asked for.
+        const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_DUAL19;
+        const bool auto_stride = cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4;
+        if (auto_stride) {
+            if (P.sampled && P.n_windows2 <= 65536) cfg.stride = 2;
+            else cfg.stride = 1;
+        }
         if (cfg.stride == 4 && !P.sampled4) cfg.stride = P.sampled ? 2 : 1;
         if (cfg.stride == 2 && !P.sampled) cfg.stride = 1;
-        if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_BITS19) {
-            // keys in the filter: prefixes (stride 1) or windows (stride 2)
+        if (auto_filter) {
+            // keys in the filter: prefixes (stride 1) or windows (strides 2, 4)
             const int64_t keys = cfg.stride == 4 ? P.n_windows4 : cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;
             const bool small_text = len < (int64_t(16) << 20);
-            const bool many = keys > 1500;
-            if (small_text) cfg.filter = many ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;
-            else cfg.filter = many ? AC_FILTER_BITS20 : AC_FILTER_BYTES17;
+            if (small_text) cfg.filter = keys > 1500 ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;
+            else if (keys <= 1500) cfg.filter = AC_FILTER_BYTES17;
+            else if (keys <= 8192) cfg.filter = AC_FILTER_BITS20;
+            else if (cfg.stride == 2 || keys > 20000) cfg.filter = AC_FILTER_DUAL19;
+            else cfg.filter = AC_FILTER_BITS20;
         }
         FilterGeom g = filter_geom(cfg.filter);
         if (filtered_lds(g) > a->lds_per_block) {
             // the 128 KiB maps need a 160 KiB LDS; fall back to the 64 KiB ones
             if (cfg.filter == AC_FILTER_BYTES17) cfg.filter = AC_FILTER_BYTES16;
-            if (cfg.filter == AC_FILTER_BITS20) cfg.filter = AC_FILTER_BITS19;
+            if (cfg.filter == AC_FILTER_BITS20 || cfg.filter == AC_FILTER_DUAL19) cfg.filter = AC_FILTER_BITS19;
             g = filter_geom(cfg.filter);
         }
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
-        // at stride 1 the bit maps need two segments to stay spill-free
-        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = (g.bitmap && cfg.stride == 1) ? 2 : 4;
+        // the bit maps at stride 1, and the dual map, need two segments to
+        // stay (nearly) spill-free
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4)
+            cfg.segs = ((g.bitmap && cfg.stride == 1) || g.dual) ? 2 : 4;
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
     } else {

@@ -24,21 +24,24 @@ constexpr int32_t kFinalBit = int32_t(0x80000000u);
 struct FilterGeom {
     int kind;        // AC_FILTER_*
     bool bitmap;     // false: one byte per entry; true: one bit per entry
-    int index_bits;  // log2(entries)
+    int index_bits;  // log2(entries) of one map
     int shift;       // product >> shift gives the byte (byte map) or word (bit map) index
     int64_t bytes;   // LDS bytes
+    bool dual;       // two bit maps with independent hashes, both must be set
 };
 
 inline FilterGeom filter_geom(int kind) {
     switch (kind) {
-        case AC_FILTER_BYTES17: return {kind, false, 17, 32 - 17, 1ll << 17};
-        case AC_FILTER_BITS20:  return {kind, true, 20, 32 - 15, 1ll << 17};
-        case AC_FILTER_BYTES16: return {kind, false, 16, 32 - 16, 1ll << 16};
-        case AC_FILTER_BITS19:  return {kind, true, 19, 32 - 14, 1ll << 16};
-        default: return {0, false, 0, 0, 0};
+        case AC_FILTER_BYTES17: return {kind, false, 17, 32 - 17, 1ll << 17, false};
+        case AC_FILTER_BITS20:  return {kind, true, 20, 32 - 15, 1ll << 17, false};
+        case AC_FILTER_BYTES16: return {kind, false, 16, 32 - 16, 1ll << 16, false};
+        case AC_FILTER_BITS19:  return {kind, true, 19, 32 - 14, 1ll << 16, false};
+        case AC_FILTER_DUAL19:  return {kind, true, 19, 32 - 14, 1ll << 17, true};
+        default: return {0, false, 0, 0, 0, false};
     }
 }
-constexpr int kNumFilterKinds = 4;
+constexpr int kNumFilterKinds = 5;
+constexpr uint32_t kFilterMul2 = 0x7FEB35u;       // hash of the second map of AC_FILTER_DUAL19
 // Filter sets: [0, 4) test every offset against the keywords' K-byte
 // prefixes; [4, 8) test odd offsets against the 3-byte windows at keyword
 // positions 0 and 1 (built when K = 3 and every keyword has >= 4 bytes).

@@ -293,6 +293,11 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
                 if (g.bitmap) {
                     uint32_t w = h >> g.shift, bit = h & 31u;
                     f[size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
+                    if (g.dual) {   // map B: the second half, its own hash
+                        const uint32_t h2 = prefix_hash(x, kFilterMul2);
+                        const uint32_t w2 = h2 >> g.shift, bit2 = h2 & 31u;
+                        f[size_t(g.bytes / 2) + size_t(w2) * 4 + bit2 / 8] |= uint8_t(1u << (bit2 % 8));
+                    }
                 } else {
                     f[size_t(h >> g.shift)] = 1;
                 }

@@ -240,7 +240,7 @@ def test_filters_have_no_false_negatives():
     assert T.info["n_windows4"] == len(key_sets[2])
     for set_, keys in key_sets.items():
         for kind, (bitmap, flog2) in geoms.items():
-            f = T.plan.export(L.AC_TABLE_FILTER_BASE + 4 * set_ + kind, np.uint8)
+            f = T.plan.export(L.AC_TABLE_FILTER_BASE + 5 * set_ + kind, np.uint8)
             assert len(f) == 1 << flog2
             for key in keys:
                 h = T.plan.hash(int.from_bytes(key, "little"))
@@ -249,12 +249,21 @@ def test_filters_have_no_false_negatives():
                     assert (int(w) >> (h & 31)) & 1
                 else:
                     assert f[h >> (32 - flog2)] == 1
+        # dual map: 2^19 bits hashed as `hash`, then 2^19 bits hashed as `hash2`
+        f = T.plan.export(L.AC_TABLE_FILTER_BASE + 5 * set_ + L.AC_FILTER_DUAL19, np.uint8).view(np.uint32)
+        assert len(f) == 2 << 14
+        for key in keys:
+            x = int.from_bytes(key, "little")
+            h1, h2 = T.plan.hash(x), T.plan.hash2(x)
+            assert h1 != h2 or x == 0
+            assert (int(f[h1 >> 18]) >> (h1 & 31)) & 1
+            assert (int(f[(1 << 14) + (h2 >> 18)]) >> (h2 & 31)) & 1
 
 
 def test_sampled_filters_need_long_enough_keywords():
     T = Tables([b"abcde", b"bcdefg"])          # shortest 5: stride 2 only
     assert T.info["n_windows2"] > 0 and T.info["n_windows4"] == 0
-    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 9, np.uint8)) == 0
+    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 12, np.uint8)) == 0
     T = Tables([b"abc", b"abcdef"])            # shortest 3: neither
     assert T.info["n_windows2"] == 0 and T.info["n_windows4"] == 0
 

@@ -54,6 +54,8 @@ POLICIES = [
     ("stride2-bits20-s4", dict(policy=1, filter=2, segs=4, stride=2)),
     ("stride2-bytes16-s1-b256", dict(policy=1, filter=3, segs=1, stride=2, block=256)),
     ("stride4-falls-back", dict(policy=1, filter=2, segs=4, stride=4)),
+    ("dual19-s4", dict(policy=1, filter=5, segs=4)),
+    ("dual19-stride1-s2-b512", dict(policy=1, filter=5, segs=2, stride=1, block=512)),
     ("direct-lds", dict(policy=2, table_in_lds=1)),
     ("direct-global", dict(policy=2, table_in_lds=2)),
 ]
