@@ -206,8 +206,21 @@ typedef struct {
 
 int ac_info(const ac_automaton *a, ac_info_t *out);
 
-/* Kernel choice the library makes for a text of `len` bytes by default. */
+/* Kernel choice the library makes for a text of `len` bytes by default
+ * (a choice recorded by ac_tune for that length, else the built-in rule). */
 int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
+
+/*
+ * Autotuner: times every choice of the filtered policy (sampling stride,
+ * filter map, segments per chunk) on d_text[0 .. len) (device; a sample of
+ * the texts to come), three runs each, and records the fastest for texts of
+ * similar length (the same floor(log4 len)).  Later single-text calls whose
+ * launch is NULL or leaves every choice at 0 use it; batches keep the
+ * built-in rule.  *out (may be NULL) receives the choice.  Synchronises
+ * `stream`; every choice computes the same matches.  Errors: AC_EINVAL
+ * (NULL automaton or text, len <= 0), AC_EHIP.
+ */
+int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t stream, ac_launch *out);
 
 const char *ac_last_error(void);
 

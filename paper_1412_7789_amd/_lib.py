@@ -22,7 +22,7 @@ EXPORTS = [
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
-    "ac_plan_hash2",
+    "ac_plan_hash2", "ac_tune",
 ]
 # every symbol include/pfac_serve.h declares
 SERVE_EXPORTS = [
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_match_batch_async": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp, vp, vp]),
         "ac_info": (ctypes.c_int, [vp, vp]),
         "ac_default_launch": (ctypes.c_int, [vp, i64, vp]),
+        "ac_tune": (ctypes.c_int, [vp, vp, i64, vp, vp]),
         "ac_last_error": (ctypes.c_char_p, []),
         "ac_compile": (ctypes.c_int, [vp, vp, i32, vp, vp]),
         "ac_plan_info": (ctypes.c_int, [vp, vp]),

@@ -133,6 +133,15 @@ class Automaton:
         L.check(L.load().ac_info(self._h, ctypes.byref(inf)), "ac_info")
         return inf.as_dict()
 
+    def tune(self, text, stream=None) -> Dict[str, int]:
+        """Time every filtered-policy choice on `text` (uint8 CUDA tensor) and
+        use the fastest for later texts of similar length."""
+        _check_text(text)
+        cfg = L.Launch()
+        L.check(L.load().ac_tune(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(), _stream_ptr(stream),
+                                 ctypes.byref(cfg)), "ac_tune")
+        return cfg.as_dict()
+
     def default_launch(self, n_bytes: int) -> Dict[str, int]:
         cfg = L.Launch()
         L.check(L.load().ac_default_launch(self._h, n_bytes, ctypes.byref(cfg)), "ac_default_launch")

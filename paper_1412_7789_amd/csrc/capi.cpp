@@ -214,9 +214,32 @@ int device_matches(const ac_automaton *a) {
 }
 
 // Enqueue zero + scan for one text or a batch.
+int length_bucket(int64_t n) {
+    int b = 0;
+    while (n >= 4) { n >>= 2; ++b; }
+    return b;
+}
+
+// Whether a launch leaves every choice to the library (NULL or all zero but
+// for the flags).
+bool all_auto(const ac_launch *l) {
+    return !l || (l->policy == 0 && l->filter == 0 && l->block == 0 && l->segs == 0 && l->grid_per_cu == 0 &&
+                  l->table_in_lds == 0 && l->stride == 0);
+}
+
 ac_launch resolved(const ac_automaton *a, const ScanArgs &S, const ac_launch *launch, bool batch) {
     ac_launch cfg{};
     if (launch) cfg = *launch;
+    if (all_auto(launch) && !batch) {
+        // a choice measured by ac_tune for texts of this length, if any
+        std::lock_guard<std::mutex> lk(a->tune_mu);
+        auto it = a->tuned.find(length_bucket(S.n));
+        if (it != a->tuned.end()) {
+            const int32_t flags = cfg.flags;
+            cfg = it->second;
+            cfg.flags = flags;
+        }
+    }
     resolve_launch(a, S.n, batch, cfg);
     return cfg;
 }
@@ -437,8 +460,9 @@ int ac_info(const ac_automaton *a, ac_info_t *out) {
 
 int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out) {
     if (!a || !out) return fail(AC_EINVAL, "ac_default_launch: NULL argument");
-    std::memset(out, 0, sizeof(*out));
-    resolve_launch(a, len, false, *out);
+    ScanArgs S{};
+    S.n = len;
+    *out = resolved(a, S, nullptr, false);
     return AC_OK;
 }
 
@@ -448,6 +472,74 @@ int64_t ac_match_ex(const ac_automaton *a, const uint8_t *d_text, int64_t len, c
     if (rc) return rc;
     if ((rc = check_launch(launch))) return rc;
     return sync_count(a, single_args(d_text, len, matches), launch, false, stream);
+}
+
+int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t stream, ac_launch *out) {
+    int rc = check_single(a, d_text, len, nullptr);
+    if (rc) return rc;
+    if (len <= 0) return fail(AC_EINVAL, "ac_tune: empty sample");
+    const Plan &P = a->host;
+    // candidate choices of the filtered policy
+    std::vector<ac_launch> cands;
+    for (int stride : {1, 2, 4}) {
+        if ((stride == 2 && !P.sampled) || (stride == 4 && !P.sampled4)) continue;
+        for (int filter = AC_FILTER_BYTES17; filter <= AC_FILTER_DUAL19; ++filter)
+            for (int segs : {1, 2, 4}) {
+                ac_launch c{};
+                c.policy = AC_POLICY_FILTERED;
+                c.filter = filter;
+                c.segs = segs;
+                c.stride = stride;
+                cands.push_back(c);
+            }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail("hipEventCreate", e);
+    float best_ms = 1e30f;
+    ac_launch best{};
+    const ScanArgs S = single_args(d_text, len, nullptr);
+    for (const ac_launch &c0 : cands) {
+        ac_launch cfg = c0;
+        resolve_launch(a, len, false, cfg);
+        if (cfg.filter != c0.filter || cfg.stride != c0.stride) continue;   // not available here
+        float ms_sum = 0.0f;
+        bool ok = true;
+        for (int rep = 0; rep < 3 && ok; ++rep) {
+            CountSlot *slot = nullptr;
+            if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) { ok = false; break; }
+            KernelTiming T;
+            T.scan0 = e0;
+            T.scan1 = e1;
+            ScanArgs SA = S;
+            SA.done = slot->d + 1;
+            slot->stale = true;                  // the next synchronous call clears the count
+            rc = enqueue(a, SA, cfg, false, true, slot->d, slot->hs, stream, &T);
+            if (rc) { ok = false; break; }
+            if ((e = hipStreamSynchronize(stream)) != hipSuccess) { rc = hip_fail("hipStreamSynchronize", e); ok = false; break; }
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail("hipEventElapsedTime", e); ok = false; break; }
+            if (rep > 0) ms_sum += ms;           // the first run warms up
+        }
+        if (!ok) break;
+        if (ms_sum < best_ms) {
+            best_ms = ms_sum;
+            best = c0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(a->tune_mu);
+        a->tuned[length_bucket(len)] = best;
+    }
+    if (out) {
+        *out = best;
+        resolve_launch(a, len, false, *out);
+    }
+    return AC_OK;
 }
 
 int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,

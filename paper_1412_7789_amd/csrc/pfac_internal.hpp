@@ -3,6 +3,8 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -136,6 +138,9 @@ struct ac_automaton {
     int cu_count = 0;
     int64_t lds_per_block = 0;
     int64_t lds_per_cu = 0;
+    // launch choices measured by ac_tune, by text-length bucket (floor(log4 len))
+    mutable std::mutex tune_mu;
+    std::map<int, ac_launch> tuned;
 };
 
 namespace pfac {

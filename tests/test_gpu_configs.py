@@ -230,3 +230,22 @@ def test_batch_graph_replays_match_eager():
         assert (per.cpu().numpy() == eper).all()
         # eager work on the default stream between replays
         assert a.count(d_texts[: int(offsets[1])]) == int(eper[0])
+
+
+def test_tune_records_a_choice_and_keeps_results():
+    """ac_tune times every filtered choice on a sample; later default calls of
+    a similar length use the choice, and every choice gives the same matches."""
+    w = config_sweep(8 * MIB)
+    a = pf.Automaton(w.keywords)
+    t = torch.from_numpy(w.text).cuda()
+    exp = Oracle(w.keywords).match(w.text)
+    before = a.default_launch(t.numel())
+    cfg = a.tune(t)
+    say("tuned", cfg, "default was", before)
+    assert cfg["policy"] == 1 and cfg["stride"] in (1, 2, 4) and cfg["segs"] in (1, 2, 4)
+    assert a.default_launch(t.numel()) == cfg
+    assert a.default_launch(t.numel() + 12345) == cfg              # same length bucket
+    assert a.default_launch(t.numel() * 64) == a.default_launch(t.numel() * 64)
+    assert_same(run_gpu(a, w.text), exp, "after tuning")
+    half = w.text[: t.numel() // 2 + 3]
+    assert_same(run_gpu(a, half), Oracle(w.keywords).match(half), "other length")
