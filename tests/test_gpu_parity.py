@@ -224,3 +224,36 @@ def test_stride4_unaligned_and_ragged(offset):
             say("stride4", offset, n, segs)
             assert_same(gpu_match(w.keywords, text, launch=cfg, offset=offset, automaton=a),
                         oracle_match(w.keywords, text), f"offset {offset} n {n} segs {segs}")
+
+
+def test_long_keywords_and_long_shared_prefixes():
+    """Keywords of 1000 and 4097 bytes (forced-path compares over many
+    16-byte rounds, a direct-policy halo of 4 KiB), keywords that share a
+    900-byte prefix and differ only at the end, and nested long keywords."""
+    rng = np.random.default_rng(21)
+    base = bytes(rng.integers(0, 256, size=4097, dtype=np.uint8))
+    kws = [base, base[:1000], base[:900] + b"\x00", base[:900] + b"\xff", base[100:1100], base[:7]]
+    text = bytearray(rng.integers(0, 256, size=300_000, dtype=np.uint8).tobytes())
+    for at in (0, 5000, 77_777, 150_001, 300_000 - 4097):
+        text[at:at + 4097] = base
+    text[200_000:200_901] = base[:900] + b"\x00"
+    text[250_000:250_901] = base[:900] + b"\xfe"          # differs in its last byte: no match
+    text = bytes(text)
+    exp = oracle_match(kws, text)
+    assert len(exp[0]) >= 15
+    for name, cfg in POLICIES:
+        say("long", name)
+        assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)), exp, f"long {name}")
+
+
+def test_binary_keywords_with_zero_bytes():
+    rng = np.random.default_rng(22)
+    kws = [b"\x00\x00\x00\x00", b"\x00\x01\x00", b"\x00" * 9, bytes(range(256)), b"\xff\x00\xff\x00"]
+    text = np.zeros(70_000, dtype=np.uint8)
+    text[10_000:10_256] = np.arange(256, dtype=np.uint8)
+    text[20_000:30_000] = rng.integers(0, 2, size=10_000, dtype=np.uint8)
+    text[40_000:40_008] = np.frombuffer(b"\xff\x00\xff\x00\xff\x00\xff\x00", dtype=np.uint8)
+    exp = oracle_match(kws, text)
+    for name, cfg in POLICIES:
+        say("binary", name)
+        assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)), exp, f"binary {name}")
