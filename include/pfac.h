@@ -129,13 +129,16 @@ typedef struct {
  * capacity; then an unspecified subset of `capacity` matches is written and
  * the caller may retry with a larger buffer.  matches == NULL counts only.
  * len == 0 returns 0.  d_text may have any alignment.
- * The call is stream-ordered on `stream` and synchronises it to return the
- * count.  The library keeps per-(device, stream) scratch (a count word and
- * the filtered policy's hit regions), allocated on the stream's first call
- * and grown when a longer text needs more; calls on one stream must come
- * from one thread at a time.  Errors: AC_EINVAL (NULL automaton, NULL text
- * with len > 0, len < 0, capacity < 0, NULL arrays with capacity > 0),
- * AC_ENOMEM, AC_EHIP.
+ * The call is stream-ordered on `stream` and returns once the count is
+ * final: the filtered scan's last block reports it to pinned host memory
+ * after every match is written (the kernel may still be retiring; work
+ * enqueued later on `stream` runs after it).  The direct policy synchronises
+ * the stream instead.  The library keeps per-(device, stream) scratch (a
+ * count word and the filtered policy's hit regions), allocated on the
+ * stream's first call and grown when a longer text needs more; calls on one
+ * stream must come from one thread at a time.  Errors: AC_EINVAL (NULL
+ * automaton, NULL text with len > 0, len < 0, capacity < 0, NULL arrays with
+ * capacity > 0), AC_ENOMEM, AC_EHIP.
  */
 int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len,
                  const ac_matches *matches, hipStream_t stream);

@@ -15,10 +15,15 @@ import numpy as np
 from . import _lib as L
 
 
-def _stream_ptr(stream) -> ctypes.c_void_p:
+def _stream_ptr(stream, device: Optional[int] = None) -> int:
+    """Raw HIP stream handle: `stream`, else the current stream of `device`
+    (default: the current device)."""
     import torch
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return stream.cuda_stream
+    if device is None:
+        device = torch.cuda.current_device()
+    return torch._C._cuda_getCurrentRawStream(device)
 
 
 def _csr(keywords: Sequence[bytes]) -> Tuple[np.ndarray, np.ndarray]:
@@ -169,12 +174,10 @@ class Automaton:
     def match_into(self, text, offsets, pattern_ids, launch: Optional[L.Launch] = None, stream=None) -> int:
         """Match into caller-owned int64/int32 CUDA tensors; returns the true count."""
         _check_text(text)
-        m = L.Matches(ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(pattern_ids.data_ptr()),
-                      min(offsets.numel(), pattern_ids.numel()))
-        return L.check(L.load().ac_match_ex(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(),
-                                            ctypes.byref(m),
+        m = L.Matches(offsets.data_ptr(), pattern_ids.data_ptr(), min(offsets.numel(), pattern_ids.numel()))
+        return L.check(L.load().ac_match_ex(self._h, text.data_ptr(), text.numel(), ctypes.byref(m),
                                             ctypes.byref(launch) if launch is not None else None,
-                                            _stream_ptr(stream)), "ac_match")
+                                            _stream_ptr(stream, text.device.index)), "ac_match")
 
     def match(self, text, capacity: Optional[int] = None, launch: Optional[L.Launch] = None, stream=None):
         """All matches of a uint8 CUDA tensor as (offsets int64, pattern_ids int32)

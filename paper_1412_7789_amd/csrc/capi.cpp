@@ -38,7 +38,8 @@ int hip_fail(const char *what, hipError_t e) {
 // it with their per-text counts.
 struct CountSlot {
     unsigned long long *d = nullptr;           // [0] match count, [1] finished blocks
-    unsigned long long *h = nullptr;
+    unsigned long long *h = nullptr;           // pinned: [0] count, [1] sequence number of the last report
+    unsigned long long seq = 0;                // last sequence number handed to a scan
     unsigned long long done_total = 0;         // value of d[1] after the last synchronous call
     bool stale = false;                        // a failed call may have left *d != *h
     hipEvent_t ev[2] = {nullptr, nullptr};   // kernel timing: scan start, stop
@@ -72,9 +73,9 @@ int count_slot(int device, hipStream_t stream, CountSlot **out, int64_t regions)
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
     // coherent: the scan kernel stores the count here itself
-    e = hipHostMalloc(reinterpret_cast<void **>(&s.h), sizeof(unsigned long long), hipHostMallocCoherent);
+    e = hipHostMalloc(reinterpret_cast<void **>(&s.h), 2 * sizeof(unsigned long long), hipHostMallocCoherent);
     if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
-    *s.h = 0;
+    s.h[0] = s.h[1] = 0;
     s.stale = true;                            // cleared by the first call
     for (auto &ev : s.ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail("hipEventCreate", e);
@@ -287,6 +288,7 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     if (clear) slot->done_total = 0;
     S.done_base = slot->done_total;
     S.host_count = reported ? slot->h : nullptr;
+    S.host_seq = ++slot->seq;
     int64_t blocks = 0;
     rc = enqueue(a, S, cfg, batch, clear, slot->d, slot->hs, stream, timed ? &T : nullptr, &blocks);
     if (rc) return rc;
@@ -295,8 +297,26 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         e = hipMemcpyAsync(slot->h, slot->d, sizeof(unsigned long long), hipMemcpyDeviceToHost, stream);
         if (e != hipSuccess) return hip_fail("hipMemcpyAsync(count)", e);
     }
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    if (reported && !timed) {
+        // The count is final once the last block has stored it with this
+        // call's sequence number; every match and per-text count is written
+        // by then.  Waiting on the word skips the stream's completion path.
+        // The stream is polled now and then, so a failed launch or a kernel
+        // that ended without reporting ends the wait too.
+        for (uint64_t spin = 1; __atomic_load_n(&slot->h[1], __ATOMIC_ACQUIRE) != S.host_seq; ++spin) {
+            __builtin_ia32_pause();
+            if (spin % 65536 != 0) continue;
+            e = hipStreamQuery(stream);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return hip_fail("hipStreamQuery", e);
+            if (__atomic_load_n(&slot->h[1], __ATOMIC_ACQUIRE) != S.host_seq)
+                return fail(AC_EHIP, "scan finished without reporting its count");
+            break;
+        }
+    } else {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    }
     if (reported) slot->done_total += uint64_t(blocks);
     slot->stale = false;
     if (timed) {
@@ -305,7 +325,7 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         g_scan_ms = g_stream_ms = ms;
         g_walk_ms = 0.0f;
     }
-    return int64_t(*slot->h - base);
+    return int64_t(__atomic_load_n(&slot->h[0], __ATOMIC_ACQUIRE) - base);
 }
 
 int check_single(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *m) {

@@ -715,7 +715,10 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         if (t == S.done_base + gridDim.x - 1) {
             __threadfence();
             const unsigned long long c = atomicAdd(S.count, 0ull);
-            *(__attribute__((address_space(1))) unsigned long long *)(S.host_count) = c;
+            auto *hc = (__attribute__((address_space(1))) unsigned long long *)(S.host_count);
+            hc[0] = c;
+            __threadfence_system();
+            hc[1] = S.host_seq;      // the count is in place
             __threadfence_system();
         }
     }

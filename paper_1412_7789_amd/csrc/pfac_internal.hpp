@@ -117,10 +117,13 @@ struct ScanArgs {
     int64_t *per_text;             // batch only, may be null
     // Optional report of the count to the host: the streaming kernel's last
     // block to finish (*done reaching done_base + blocks) stores *count into
-    // host_count, a pinned host word.  host_count == nullptr: no report.
+    // host_count[0], a pinned host word, and then host_seq into host_count[1],
+    // so the host can wait for the word instead of the stream.
+    // host_count == nullptr: no report.
     unsigned long long *done;
     unsigned long long done_base;
     unsigned long long *host_count;
+    unsigned long long host_seq;
 };
 
 }  // namespace pfac
