@@ -242,24 +242,35 @@ __device__ __forceinline__ uint2 prefix_state(LoadBucket load, int bits, uint32_
 }
 
 // Text of a candidate offset: [start, end) of the text holding o and its id.
-__device__ __forceinline__ void locate_text(const ScanArgs &S, int64_t o, int64_t &tstart, int64_t &end,
-                                            int32_t &tid) {
+// A batch's text starts come from `loff` when the block has copied them to
+// LDS (as offsets from the first text, all below 2^32), else from global
+// memory.
+__device__ __forceinline__ void locate_text(const ScanArgs &S, const uint32_t *loff, int64_t o, int64_t &tstart,
+                                            int64_t &end, int32_t &tid) {
     tstart = 0;
     end = S.n;
     tid = 0;
-    if (S.text_off) {
-        // largest t with text_off[t] - text_off[0] <= o
+    if (!S.text_off) return;
+    int32_t lo = 0, hi = S.n_texts;   // largest t with start(t) <= o, in [lo, hi)
+    if (loff) {
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (int64_t(loff[mid]) <= o) lo = mid;
+            else hi = mid;
+        }
+        tstart = loff[lo];
+        end = lmin(int64_t(loff[lo + 1]), S.n);
+    } else {
         const int64_t base0 = S.text_off[0];
-        int32_t lo = 0, hi = S.n_texts;   // answer in [lo, hi)
         while (hi - lo > 1) {
             const int32_t mid = (lo + hi) >> 1;
             if (S.text_off[mid] - base0 <= o) lo = mid;
             else hi = mid;
         }
-        tid = lo;
         tstart = S.text_off[lo] - base0;
         end = lmin(S.text_off[lo + 1] - base0, S.n);
     }
+    tid = lo;
 }
 
 // 16 bytes from p, of any alignment, assembled from five aligned dword loads.
@@ -322,7 +333,7 @@ __device__ __forceinline__ bool equal_bytes(const uint8_t *t, const uint8_t *k, 
 // starting at o.
 template <bool REC, bool STAGED>
 __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, const uint8_t *cls, int64_t o,
-                                          uint32_t e, uint2 rb, MatchStage *st) {
+                                          uint32_t e, uint2 rb, MatchStage *st, const uint32_t *loff = nullptr) {
     auto out = [&](int64_t off, int32_t tid, int32_t state) __attribute__((always_inline)) {
         if (STAGED) emit_staged(A, S, st, off, tid, state);
         else emit(A, S, off, tid, state);
@@ -330,7 +341,7 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
     const int K = A.K;
     int64_t tstart, end;
     int32_t tid;
-    locate_text(S, o, tstart, end, tid);
+    locate_text(S, loff, o, tstart, end, tid);
     if (o + K > end) return;          // the prefix ran into the next text of a batch
     auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
         if (REC) {
@@ -697,6 +708,20 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     __syncthreads();
     const int32_t total = wfirst[waves_per_block];
     const int64_t r0 = int64_t(blockIdx.x) * waves_per_block;
+    // A batch's text starts (as offsets from the first text) are copied to
+    // LDS when they fit, beside the stage or where the prefix table was, so
+    // the walks look their texts up there.
+    constexpr int kStageEnd = ((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 + 15) / 16 * 16;
+    constexpr int kLdsTexts = FLOG2 >= 17 ? ((1 << FLOG2) - kStageEnd) / 4 : 2 * PT_SLOTS;
+    static_assert(kLdsTexts >= 4096, "room for the text starts of a batch of 4096 texts");
+    uint32_t *lds_off = FLOG2 >= 17 ? reinterpret_cast<uint32_t *>(sfilt + kStageEnd) : sptab;
+    const uint32_t *loff = nullptr;
+    if (S.text_off && total > 0 && S.n_texts < kLdsTexts && S.n < (int64_t(1) << 32)) {
+        const int64_t base0 = S.text_off[0];
+        for (int i = int(threadIdx.x); i <= S.n_texts; i += int(blockDim.x)) lds_off[i] = uint32_t(S.text_off[i] - base0);
+        __syncthreads();
+        loff = lds_off;
+    }
     for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
         int j = 0;
         while (wfirst[j + 1] <= i) ++j;          // wave (region) of flat index i
@@ -704,7 +729,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
         if ((rec.x >> 12) >= wkmin[j]) continue;   // walked by that wave's post-pass
         const int64_t chunk = F.c_lo + r0 + j + int64_t(rec.x >> 12) * nw;
         const int64_t o = chunk * CH + int64_t(rec.x & 4095u) - F.mis;
-        walk_rest<true, true>(A, S, A.cls, o, rec.y, make_uint2(rec.z, rec.w), st);
+        walk_rest<true, true>(A, S, A.cls, o, rec.y, make_uint2(rec.z, rec.w), st, loff);
     }
     flush_stage(S, st);
 

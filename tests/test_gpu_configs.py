@@ -189,6 +189,31 @@ def test_batch_edge_cases():
         assert (per == np.bincount(et, minlength=len(texts))).all()
 
 
+@pytest.mark.parametrize("n_texts", [12000, 16383, 16384, 24000])
+def test_batch_text_lookup_in_lds_and_global(n_texts):
+    """Walks find their text by a binary search over the text starts, in LDS
+    when the batch's starts fit beside the match stage (fewer than 16384
+    texts with the 64 KiB maps, about 20400 with the 128 KiB maps), else in
+    global memory: both sides of each limit against the oracle."""
+    w = config_batched()
+    rng = np.random.default_rng(n_texts)
+    lens = rng.integers(0, 700, size=n_texts)
+    offsets = np.zeros(n_texts + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    texts = w.texts[: int(offsets[-1])].copy()
+    a = pf.Automaton(w.keywords)
+    et, eo, ep = batch_expected(w.keywords, texts, offsets)
+    d_texts = torch.from_numpy(texts).cuda()
+    d_offs = torch.from_numpy(offsets).cuda()
+    for cfg in (None, dict(policy=1, filter=2), dict(policy=1, filter=4, stride=1)):
+        say("batch lookup", n_texts, cfg)
+        launch = pf.launch_config(**cfg) if cfg else None
+        tid, off, pid, per = (x.cpu().numpy() for x in a.match_batch(d_texts, d_offs, launch=launch))
+        assert len(tid) == len(et)
+        assert (batch_key(tid, off, pid) == batch_key(et, eo, ep)).all(), str(cfg)
+        assert (per == np.bincount(et, minlength=n_texts)).all(), str(cfg)
+
+
 def test_batch_graph_replays_match_eager():
     """The asynchronous batch call captured in a HIP graph: every replay, with
     eager calls on other streams in between, gives the eager result."""
