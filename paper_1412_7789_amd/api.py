@@ -15,15 +15,13 @@ import numpy as np
 from . import _lib as L
 
 
-def _stream_ptr(stream, device: Optional[int] = None) -> int:
-    """Raw HIP stream handle: `stream`, else the current stream of `device`
-    (default: the current device)."""
+def _stream_ptr(stream) -> int:
+    """Raw HIP stream handle: `stream`, else the current device's current
+    stream."""
     import torch
     if stream is not None:
         return stream.cuda_stream
-    if device is None:
-        device = torch.cuda.current_device()
-    return torch._C._cuda_getCurrentRawStream(device)
+    return torch._C._cuda_getCurrentRawStream(torch.cuda.current_device())
 
 
 def _csr(keywords: Sequence[bytes]) -> Tuple[np.ndarray, np.ndarray]:
@@ -177,7 +175,7 @@ class Automaton:
         m = L.Matches(offsets.data_ptr(), pattern_ids.data_ptr(), min(offsets.numel(), pattern_ids.numel()))
         return L.check(L.load().ac_match_ex(self._h, text.data_ptr(), text.numel(), ctypes.byref(m),
                                             ctypes.byref(launch) if launch is not None else None,
-                                            _stream_ptr(stream, text.device.index)), "ac_match")
+                                            _stream_ptr(stream)), "ac_match")
 
     def match(self, text, capacity: Optional[int] = None, launch: Optional[L.Launch] = None, stream=None):
         """All matches of a uint8 CUDA tensor as (offsets int64, pattern_ids int32)
@@ -215,8 +213,7 @@ class Automaton:
         m = L.BatchMatches(ctypes.c_void_p(text_ids.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
                            ctypes.c_void_p(pattern_ids.data_ptr()), cap,
                            ctypes.c_void_p(per_text.data_ptr()) if per_text is not None else None)
-        return L.check(L.load().ac_match_batch(self._h, ctypes.c_void_p(texts.data_ptr()),
-                                               ctypes.c_void_p(text_offsets.data_ptr()), n_texts, total,
+        return L.check(L.load().ac_match_batch(self._h, texts.data_ptr(), text_offsets.data_ptr(), n_texts, total,
                                                ctypes.byref(m),
                                                ctypes.byref(launch) if launch is not None else None,
                                                _stream_ptr(stream)), "ac_match_batch")
