@@ -294,6 +294,15 @@ __device__ __forceinline__ u32x4 load16_clamped(const uint8_t *p, uintptr_t last
     return r;
 }
 
+// 16 bytes from p, of any alignment, in one load: global memory is accessed
+// in the GPU's unaligned access mode, which ROCm enables.  [p, p + 16) must
+// be readable.
+__device__ __forceinline__ u32x4 load16_any(const uint8_t *p) {
+    u32x4 r;
+    __builtin_memcpy(&r, (const __attribute__((address_space(1))) uint8_t *)(p), 16);
+    return r;
+}
+
 // XOR of the first n (0..16) bytes of a and b, 0 when they agree.
 __device__ __forceinline__ uint32_t diff16(u32x4 a, u32x4 b, int n) {
     uint32_t d = 0;
@@ -308,18 +317,22 @@ __device__ __forceinline__ uint32_t diff16(u32x4 a, u32x4 b, int n) {
 
 // Whether text t[0 .. n) equals keyword bytes k[0 .. n) (n <= 64; text[0 ..
 // text_n) is the scanned buffer, which holds t[0 .. n)).  The first 32 bytes
-// of both are loaded in one round trip; longer tails take more.  Keyword
-// bytes may be read up to 67 bytes past a keyword: the keyword section is
-// followed by at least 256 bytes of the same allocation.
+// of both are loaded in one round trip, as 16-byte loads of any alignment;
+// longer tails take more.  Text bytes within 16 of the buffer's end come
+// from clamped dword loads instead.  Keyword bytes may be read up to 79
+// bytes past a keyword: the keyword section is followed by at least 256
+// bytes of the same allocation.
 __device__ __forceinline__ bool equal_bytes(const uint8_t *t, const uint8_t *k, int n, const uint8_t *text,
                                             int64_t text_n) {
-    const uintptr_t tlast = (reinterpret_cast<uintptr_t>(text) + uintptr_t(text_n) - 1u) & ~uintptr_t(3);
-    const uintptr_t klast = ~uintptr_t(0);
-    const u32x4 t0 = load16_clamped(t, tlast), t1 = load16_clamped(t + 16, tlast);
-    const u32x4 k0 = load16_clamped(k, klast), k1 = load16_clamped(k + 16, klast);
+    const uintptr_t tend = reinterpret_cast<uintptr_t>(text) + uintptr_t(text_n);
+    const uintptr_t tlast = (tend - 1u) & ~uintptr_t(3);
+    auto text16 = [&](const uint8_t *p) __attribute__((always_inline)) {
+        return reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p) : load16_clamped(p, tlast);
+    };
+    const u32x4 t0 = text16(t), t1 = text16(t + 16);
+    const u32x4 k0 = load16_any(k), k1 = load16_any(k + 16);
     uint32_t d = diff16(t0, k0, n) | diff16(t1, k1, n - 16);
-    for (int i = 32; d == 0 && i < n; i += 16)
-        d = diff16(load16_clamped(t + i, tlast), load16_clamped(k + i, klast), n - i);
+    for (int i = 32; d == 0 && i < n; i += 16) d = diff16(text16(t + i), load16_any(k + i), n - i);
     return d == 0;
 }
 
@@ -733,12 +746,17 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const Sc
     }
     flush_stage(S, st);
 
-    // The last block to finish hands the count to the host.
+    // The last block to finish hands the count to the host, once every
+    // block's matches are stored: the barrier waits for this block's stores,
+    // the release fence makes them visible to the device before the block
+    // counts itself done, and the last block's acquire fence pairs with the
+    // other blocks' release fences.
+    if (S.host_count) __syncthreads();
     if (S.host_count && threadIdx.x == 0) {
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const unsigned long long t = atomicAdd(S.done, 1ull);
         if (t == S.done_base + gridDim.x - 1) {
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const unsigned long long c = atomicAdd(S.count, 0ull);
             auto *hc = (__attribute__((address_space(1))) unsigned long long *)(S.host_count);
             hc[0] = c;
@@ -931,12 +949,14 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
         // Texts under 32 MiB take one segment per wave step, which spreads
         // them over more waves (measured on MI355X: a 1 MiB scan in 11 us
-        // instead of 19 with four segments).  Above that, the bit maps at
-        // stride 1, and the dual map, need two segments to stay (nearly)
-        // spill-free; the others take four.
+        // instead of 19 with four segments).  Above that, the single bit map
+        // at stride 1 takes two segments (four spill and ran 8% slower on
+        // 50000 keywords); the others take four, the dual map too (its
+        // four-segment kernels spill a little but ran 1-2% faster than two
+        // on 20000 and 50000 keywords).
         if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) {
             if (len < (int64_t(32) << 20)) cfg.segs = 1;
-            else cfg.segs = ((g.bitmap && cfg.stride == 1) || g.dual) ? 2 : 4;
+            else cfg.segs = (g.bitmap && !g.dual && cfg.stride == 1) ? 2 : 4;
         }
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);

@@ -71,6 +71,24 @@ def check_windows(keywords, text, off, pid, n_windows=6, width=4 * MIB, seed=0):
     o_or.close()
 
 
+def count_overlapping(text_bytes, k):
+    """Occurrences of k in the text, overlapping ones included (bytes.find)."""
+    n, i = 0, text_bytes.find(k)
+    while i >= 0:
+        n += 1
+        i = text_bytes.find(k, i + 1)
+    return n
+
+
+def check_sampled_counts(keywords, text, pid, n_keywords=20, seed=0):
+    """Per-keyword match counts over the whole text equal a plain substring
+    count for a sample of keywords."""
+    tb = text.tobytes()
+    got = np.bincount(pid, minlength=len(keywords))
+    for p in np.random.default_rng(seed).choice(len(keywords), size=n_keywords, replace=False):
+        assert got[p] == count_overlapping(tb, keywords[p]), f"keyword {p}"
+
+
 def check_plants(keywords, text, off, pid, plants):
     got = set(zip(off.tolist(), pid.tolist()))
     for o, p in plants:
@@ -107,6 +125,7 @@ def test_sweep_1gib_launch():
     check_sound(w.keywords, w.text, off, pid)
     check_plants(w.keywords, w.text, off, pid, w.plants)
     check_windows(w.keywords, w.text, off, pid)
+    check_sampled_counts(w.keywords, w.text, pid)
 
 
 def test_large_automaton_64mib_full():
@@ -132,6 +151,26 @@ def test_large_automaton_1gib_launch():
     check_sound(w.keywords, w.text, off, pid)
     check_plants(w.keywords, w.text, off, pid, w.plants)
     check_windows(w.keywords, w.text, off, pid, n_windows=4)
+    check_sampled_counts(w.keywords, w.text, pid)
+
+
+def test_pid_permutation_and_keyword_subsets():
+    """Renumbering the keywords renumbers the matches and nothing else, and an
+    automaton of a subset of the keywords finds exactly the full set's
+    matches of those keywords (the subsets get their own filter choices)."""
+    w = config_sweep(64 * MIB)
+    n = len(w.keywords)
+    full = run_gpu(pf.Automaton(w.keywords), w.text)
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(n)
+    off, pid = run_gpu(pf.Automaton([w.keywords[i] for i in perm]), w.text)
+    assert_same((off, perm[pid]), full, "permuted keyword ids")
+    for size in (10, 300, 999):
+        sub = np.sort(rng.choice(n, size=size, replace=False))
+        say("subset", size)
+        off, pid = run_gpu(pf.Automaton([w.keywords[i] for i in sub]), w.text)
+        sel = np.isin(full[1], sub)
+        assert_same((off, sub[pid]), (full[0][sel], full[1][sel]), f"subset of {size}")
 
 
 def batch_expected(keywords, texts, offsets):
