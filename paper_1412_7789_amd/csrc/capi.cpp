@@ -304,7 +304,9 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         // The stream is polled now and then, so a failed launch or a kernel
         // that ended without reporting ends the wait too.
         for (uint64_t spin = 1; __atomic_load_n(&slot->h[1], __ATOMIC_ACQUIRE) != S.host_seq; ++spin) {
+#if defined(__x86_64__)
             __builtin_ia32_pause();
+#endif
             if (spin % 65536 != 0) continue;
             e = hipStreamQuery(stream);
             if (e == hipErrorNotReady) continue;
