@@ -257,3 +257,35 @@ def test_binary_keywords_with_zero_bytes():
     for name, cfg in POLICIES:
         say("binary", name)
         assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)), exp, f"binary {name}")
+
+
+def test_concurrent_host_threads_on_their_own_streams():
+    """Synchronous calls from four host threads at once, each on its own
+    stream (its own count word and hit regions) and text, with one shared
+    automaton: every call gives the oracle's result for its text."""
+    import threading
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    slices = [w.text[s:s + (1 << 18) + 7 * s] for s in (0, 3, 100_001, 500_000)]
+    exp = [oracle_match(w.keywords, s) for s in slices]
+    errors = []
+
+    def worker(t):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                d = torch.from_numpy(slices[t]).cuda()
+                for r in range(12):
+                    off, pid = a.match(d, stream=s)
+                    assert_same((off.cpu().numpy(), pid.cpu().numpy()), exp[t], f"thread {t} call {r}")
+                    assert a.count(d, stream=s) == len(exp[t][0])
+        except Exception as e:          # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    assert not any(th.is_alive() for th in threads), "a worker did not finish"
+    assert not errors, errors[0]
