@@ -289,3 +289,22 @@ def test_concurrent_host_threads_on_their_own_streams():
         th.join(timeout=120)
     assert not any(th.is_alive() for th in threads), "a worker did not finish"
     assert not errors, errors[0]
+
+
+def test_every_offset_matches_closed_form():
+    """A text of one repeated byte with keywords c^L: every offset is a
+    candidate and a hit, walks run 32 states deep past keywords ending on the
+    way, and every wave's hit region overflows.  The full match set against
+    the oracle at 1 MiB; the count against the closed form sum(N - L + 1) at
+    64 MiB, for the default launch and each segment count."""
+    kws = [b"a" * L for L in (1, 2, 4, 9, 32)] + [b"ab"]
+    a = pf.Automaton(kws)
+    small = np.full(1 << 20, ord("a"), dtype=np.uint8)
+    say("every offset, 1 MiB")
+    assert_same(gpu_match(kws, small, automaton=a), oracle_match(kws, small), "1 MiB of a")
+    n = 64 << 20
+    t = torch.full((n,), ord("a"), dtype=torch.uint8, device="cuda")
+    exp = sum(n - len(k) + 1 for k in kws[:-1])
+    for cfg in (None, dict(policy=1, segs=1), dict(policy=1, segs=2), dict(policy=1, segs=4)):
+        say("every offset, 64 MiB", cfg)
+        assert a.count(t, launch=pf.launch_config(**cfg) if cfg else None) == exp, str(cfg)
