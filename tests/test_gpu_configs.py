@@ -313,3 +313,29 @@ def test_tune_records_a_choice_and_keeps_results():
     assert_same(run_gpu(a, w.text), exp, "after tuning")
     half = w.text[: t.numel() // 2 + 3]
     assert_same(run_gpu(a, half), Oracle(w.keywords).match(half), "other length")
+
+
+@pytest.mark.parametrize("n_texts", [5000, 20000])
+def test_batch_of_one_byte_texts_closed_form(n_texts):
+    """Texts of one repeated byte with keywords c^1, c^3, c^7: text i of
+    length L holds max(0, L - k + 1) matches of c^k and no match may run into
+    the next text.  Per-text counts against that closed form, and every
+    reported match inside its own text; on both sides of the LDS limit of the
+    walks' text lookup."""
+    kws = [b"a", b"aaa", b"a" * 7]
+    klen = np.array([len(k) for k in kws])
+    rng = np.random.default_rng(n_texts + 1)
+    lens = rng.integers(0, 200, size=n_texts)
+    offsets = np.zeros(n_texts + 1, dtype=np.int64)
+    np.cumsum(lens, out=offsets[1:])
+    texts = np.full(int(offsets[-1]), ord("a"), dtype=np.uint8)
+    a = pf.Automaton(kws)
+    tid, off, pid, per = (x.cpu().numpy() for x in a.match_batch(torch.from_numpy(texts).cuda(),
+                                                                  torch.from_numpy(offsets).cuda()))
+    exp = sum(np.maximum(0, lens - L + 1) for L in klen)
+    assert (per == exp).all()
+    assert len(tid) == int(exp.sum())
+    assert (off >= 0).all() and (off + klen[pid] <= lens[tid]).all()
+    # no (text, offset, keyword) reported twice
+    key = (tid.astype(np.int64) << 40) | (off.astype(np.int64) << 8) | pid
+    assert len(np.unique(key)) == len(key)
