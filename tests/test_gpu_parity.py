@@ -308,3 +308,35 @@ def test_every_offset_matches_closed_form():
     for cfg in (None, dict(policy=1, segs=1), dict(policy=1, segs=2), dict(policy=1, segs=4)):
         say("every offset, 64 MiB", cfg)
         assert a.count(t, launch=pf.launch_config(**cfg) if cfg else None) == exp, str(cfg)
+
+
+def test_single_text_graph_replays_match_eager():
+    """The asynchronous single-text call (clearing kernel + scan) captured in
+    a HIP graph: each replay, with eager synchronous calls on the default
+    stream in between, writes the oracle's match set and count again."""
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    text = w.text[: (1 << 19) + 5]
+    exp = oracle_match(w.keywords, text)
+    n = len(exp[0])
+    t = torch.from_numpy(text).cuda()
+    off = torch.empty(n + 8, dtype=torch.int64, device="cuda")
+    pid = torch.empty(n + 8, dtype=torch.int32, device="cuda")
+    d_count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.match_async(t, off, pid, d_count, stream=s)     # sizes the stream's scratch before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.match_async(t, off, pid, d_count, stream=s)
+    for r in range(4):
+        say("single graph replay", r)
+        off.fill_(-1)
+        pid.fill_(-1)
+        d_count.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(d_count.item()) == n
+        assert_same((off[:n].cpu().numpy(), pid[:n].cpu().numpy()), exp, f"replay {r}")
+        assert a.count(t) == n                              # eager work between replays
