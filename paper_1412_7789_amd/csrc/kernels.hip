@@ -38,7 +38,7 @@ namespace pfac {
 namespace {
 
 constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
-constexpr int kDrain = 192;      // candidates taken per drain (3 per lane)
+constexpr int kDrain = 64;       // candidates taken per drain (1 per lane; 128 and 192 measured slower)
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
