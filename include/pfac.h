@@ -96,6 +96,11 @@ typedef struct {
 #define AC_FILTER_BITS19    4  /* 2^19-bit map, 64 KiB of LDS                   */
 #define AC_FILTER_DUAL19    5  /* two 2^19-bit maps with independent hashes,   */
                                /* 128 KiB of LDS; both bits must be set         */
+#define AC_FILTER_PAIR20    6  /* stride 4 only: a 2^20-bit map (128 KiB of LDS) */
+                               /* keyed by the keywords' 4-byte windows at      */
+                               /* positions 1 .. 4, two bits per key in one     */
+                               /* word: both must be set; needs every keyword   */
+                               /* >= 8 bytes                                    */
 
 typedef struct {
     int32_t policy;         /* AC_POLICY_*                                        */
@@ -106,13 +111,13 @@ typedef struct {
     int32_t table_in_lds;   /* DIRECT: -1/0 = auto, 1 = force LDS, 2 = global     */
     int32_t flags;          /* AC_LAUNCH_* bits                                   */
     int32_t stride;         /* FILTERED: 1 = test every offset's prefix; 2 = test
-                             * every second offset against the keywords' 3-byte
-                             * windows at positions 0 and 1 (needs every keyword
-                             * >= 4 bytes), a positive test making the offset and
-                             * the one before it candidates; 4 = every fourth
-                             * offset against the windows at positions 0 .. 3
-                             * (keywords >= 6 bytes), a positive making it and the
-                             * three before it candidates; 0 = auto              */
+                             * the 3-byte windows starting at every second offset
+                             * against the keywords' windows at positions 1 and 2
+                             * (needs every keyword >= 5 bytes), a positive test at
+                             * s making s - 2 and s - 1 candidates; 4 = every
+                             * fourth window against the windows at positions
+                             * 1 .. 4 (keywords >= 7 bytes), a positive at s making
+                             * s - 4 .. s - 1 candidates; 0 = auto               */
     int32_t reserved[4];
 } ac_launch;
 
@@ -198,13 +203,14 @@ typedef struct {
     int32_t n_dense_states;  /* states [0, n_dense_states) have dense rows      */
     int32_t dense_depth;     /* every state of depth <= dense_depth is dense    */
     int32_t n_prefixes;      /* distinct keyword prefixes of prefix_len bytes   */
-    int32_t n_windows2;      /* distinct 3-byte windows at positions 0 and 1 (0 = stride 2 unavailable) */
+    int32_t n_windows2;      /* distinct 3-byte windows at positions 1 and 2 (0 = stride 2 unavailable) */
     int64_t dense_bytes, compact_bytes, output_bytes, filter_bytes, device_bytes;
     double build_ms;         /* host build + upload time                        */
     int64_t prefix_table_bytes;  /* exact prefix -> state table                 */
     int64_t tail_bytes;      /* forced-path leaves + keyword bytes               */
-    int32_t n_windows4;      /* distinct 3-byte windows at positions 0 .. 3 (0 = stride 4 unavailable) */
-    int32_t reserved[3];
+    int32_t n_windows4;      /* distinct 3-byte windows at positions 1 .. 4 (0 = stride 4 unavailable) */
+    int32_t n_quads4;        /* distinct 4-byte windows at positions 1 .. 4 (0 = AC_FILTER_PAIR20 unavailable) */
+    int32_t reserved[2];
 } ac_info_t;
 
 int ac_info(const ac_automaton *a, ac_info_t *out);
@@ -271,10 +277,16 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                                          the leaf's only keyword id + 1 or 0}; first
  *                                          field -2 at a leaf, -1 without a forced path
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
- *                              k = 5 + AC_FILTER_* (stride 2, may be empty),
- *                              k = 10 + AC_FILTER_* (stride 4, may be empty);
+ *                              k = 6 + AC_FILTER_* (stride 2, may be empty),
+ *                              k = 12 + AC_FILTER_* (stride 4, may be empty);
  *                              AC_FILTER_DUAL19: map A (first 64 KiB, hashed as
- *                              ac_plan_hash) then map B (ac_plan_hash2)
+ *                              ac_plan_hash) then map B (ac_plan_hash2).  A key
+ *                              with hash h owns bit h mod 32 of word (or byte)
+ *                              h >> shift; the stride-2 and stride-4 maps also
+ *                              set it at index (h + 31) >> shift.
+ *                              AC_FILTER_PAIR20 (stride 4 only): the 4-byte
+ *                              window x owns bits h mod 32 and (x >> 24) mod 32
+ *                              of word h >> 17, h = ac_plan_hash(x)
  */
 #define AC_TABLE_CLASS_MAP  1
 #define AC_TABLE_DENSE      2

@@ -12,6 +12,7 @@ AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_ENOTSUP = 0, -1, -2, -3, -4
 AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
 AC_FILTER_AUTO, AC_FILTER_BYTES17, AC_FILTER_BITS20, AC_FILTER_BYTES16, AC_FILTER_BITS19 = 0, 1, 2, 3, 4
 AC_FILTER_DUAL19 = 5
+AC_FILTER_PAIR20 = 6
 AC_TABLE_CLASS_MAP, AC_TABLE_DENSE, AC_TABLE_NODE, AC_TABLE_LABEL = 1, 2, 3, 4
 AC_TABLE_OUT_OFF, AC_TABLE_OUT_PID, AC_TABLE_DEPTH, AC_TABLE_FILTER_BASE = 5, 6, 7, 100
 AC_TABLE_PREFIX, AC_TABLE_TAIL, AC_TABLE_TAIL_INFO = 8, 9, 10
@@ -66,7 +67,7 @@ class Info(ctypes.Structure):
                 ("output_bytes", ctypes.c_int64), ("filter_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
                 ("prefix_table_bytes", ctypes.c_int64), ("tail_bytes", ctypes.c_int64),
-                ("n_windows4", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("n_windows4", ctypes.c_int32), ("n_quads4", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}

@@ -31,11 +31,13 @@ int hip_fail(const char *what, hipError_t e) {
 }
 
 // One device count word and one pinned host word per (device, stream),
-// allocated on first use and kept for the life of the process.  The
-// synchronous calls never clear the device word: it only grows, the pinned
-// word holds its value after the last such call, and a scan numbers its
-// matches from that value on (ScanArgs::count_base).  The batch calls clear
-// it with their per-text counts.
+// allocated on first use and kept until the stream's scratch is released.
+// The synchronous calls never clear the device word: it only grows, the
+// pinned word holds its value after the last such call, and a scan numbers
+// its matches from that value on (ScanArgs::count_base).  The batch calls
+// clear it with their per-text counts.  The filtered policy's hit regions
+// are sized for the widest launch when the slot is created and never change
+// afterwards, so a HIP graph that captured their address stays valid.
 struct CountSlot {
     unsigned long long *d = nullptr;           // [0] match count, [1] finished blocks
     unsigned long long *h = nullptr;           // pinned: [0] count, [1] sequence number of the last report
@@ -46,55 +48,61 @@ struct CountSlot {
     HitScratch hs;                             // hit regions of the filtered policy
 };
 std::mutex g_slots_mu;
-std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;   // entries are never erased
+std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
 
-// Grows the slot's hit regions to at least `regions` (never shrinks).
-int ensure_hits(CountSlot &s, int64_t regions) {
-    if (s.hs.regions >= regions) return AC_OK;
+void free_slot(CountSlot &s) {
+    if (s.d) (void)hipFree(s.d);
+    if (s.h) (void)hipHostFree(s.h);
+    for (hipEvent_t ev : s.ev)
+        if (ev) (void)hipEventDestroy(ev);
     if (s.hs.hits) (void)hipFree(s.hs.hits);
-    s.hs = HitScratch();
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.hs.hits), size_t(regions) * kHitCap * sizeof(uint4));
-    if (e != hipSuccess) return fail(AC_ENOMEM, std::string("hipMalloc(hit regions): ") + hipGetErrorString(e));
-    s.hs.regions = regions;
-    s.hs.cap = kHitCap;
-    return AC_OK;
+    s = CountSlot();
 }
 
-// The slot of (device, stream), created on first use; the pointer stays valid.
+// The slot of (device, stream), created on first use with hit regions for
+// `regions` waves (the widest launch on the device); the pointer stays valid
+// until the slot is released.
 int count_slot(int device, hipStream_t stream, CountSlot **out, int64_t regions) {
     std::lock_guard<std::mutex> lk(g_slots_mu);
     auto key = std::make_pair(device, stream);
     auto it = g_slots.find(key);
     if (it != g_slots.end()) {
         *out = &it->second;
-        return ensure_hits(it->second, regions);
+        return it->second.hs.regions >= regions ? AC_OK
+                                                : fail(AC_EINVAL, "stream scratch has fewer hit regions than the launch");
     }
     CountSlot s;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&s.d), 2 * sizeof(unsigned long long));
     if (e != hipSuccess) return hip_fail("hipMalloc(count)", e);
     // coherent: the scan kernel stores the count here itself
     e = hipHostMalloc(reinterpret_cast<void **>(&s.h), 2 * sizeof(unsigned long long), hipHostMallocCoherent);
-    if (e != hipSuccess) { (void)hipFree(s.d); return hip_fail("hipHostMalloc(count)", e); }
+    if (e != hipSuccess) { free_slot(s); return hip_fail("hipHostMalloc(count)", e); }
     s.h[0] = s.h[1] = 0;
     s.stale = true;                            // cleared by the first call
     for (auto &ev : s.ev)
-        if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail("hipEventCreate", e);
+        if ((e = hipEventCreate(&ev)) != hipSuccess) { free_slot(s); return hip_fail("hipEventCreate", e); }
+    e = hipMalloc(reinterpret_cast<void **>(&s.hs.hits), size_t(regions) * kHitCap * sizeof(uint4));
+    if (e != hipSuccess) { free_slot(s); return fail(AC_ENOMEM, std::string("hipMalloc(hit regions): ") + hipGetErrorString(e)); }
+    s.hs.regions = regions;
+    s.hs.cap = kHitCap;
     CountSlot &slot = g_slots[key];
     slot = s;
     *out = &slot;
-    return ensure_hits(slot, regions);
+    return AC_OK;
+}
+
+// The calling stream's slot, with hit regions for any launch on a's device.
+int slot_for(const ac_automaton *a, hipStream_t stream, CountSlot **out) {
+    return count_slot(a->device, stream, out, widest_scan_regions(a->cu_count, a->lds_per_cu));
 }
 
 int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
 
-int upload(ac_automaton *a) {
-    const Plan &P = a->host;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
-    a->device = dev;
-    int cus = 0, lds = 0, lds_optin = 0;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+// Compute units and LDS bytes (per block, per CU) of device `dev`.
+int device_props(int dev, int *cus, int64_t *lds_block, int64_t *lds_cu) {
+    int c = 0, lds = 0, lds_optin = 0, per_cu = 0;
+    hipError_t e;
+    if ((e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail("hipDeviceGetAttribute(cu)", e);
     if ((e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
         return hip_fail("hipDeviceGetAttribute(lds)", e);
@@ -102,14 +110,24 @@ int upload(ac_automaton *a) {
         lds_optin = 0;
         (void)hipGetLastError();
     }
-    int lds_cu = 0;
-    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
-        lds_cu = 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
+        per_cu = 0;
         (void)hipGetLastError();
     }
-    a->cu_count = std::max(1, cus);
-    a->lds_per_block = std::max(lds, lds_optin);
-    a->lds_per_cu = std::max<int64_t>(lds_cu, a->lds_per_block);
+    *cus = std::max(1, c);
+    *lds_block = std::max(lds, lds_optin);
+    *lds_cu = std::max<int64_t>(per_cu, *lds_block);
+    return AC_OK;
+}
+
+int upload(ac_automaton *a) {
+    const Plan &P = a->host;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    a->device = dev;
+    int rc = device_props(dev, &a->cu_count, &a->lds_per_block, &a->lds_per_cu);
+    if (rc) return rc;
 
     // section layout (each section 256-byte aligned and padded)
     struct Sec { const void *src; int64_t bytes; int64_t at; };
@@ -146,23 +164,19 @@ int upload(ac_automaton *a) {
     uint8_t *b = static_cast<uint8_t *>(a->dmem);
     DevAut &D = a->dev;
     D.cls = b + cls.at;
-    for (int k = 0; k < kNumFilters; ++k) D.filter[k] = b + filt[k].at;
+    for (int k = 0; k < kNumFilters; ++k) a->dfilter[k] = b + filt[k].at;
     D.dense = reinterpret_cast<const int32_t *>(b + dense.at);
     D.node = reinterpret_cast<const int32_t *>(b + node.at);
     D.label = b + label.at;
     D.out_off = reinterpret_cast<const int32_t *>(b + ooff.at);
     D.out_pid = reinterpret_cast<const int32_t *>(b + opid.at);
     D.ptab = reinterpret_cast<const uint32_t *>(b + ptab.at);
-    D.tail = reinterpret_cast<const int32_t *>(b + tail.at);
     D.tailinfo = reinterpret_cast<const int4 *>(b + tinfo.at);
     D.kw_bytes = b + kwb.at;
-    D.kw_off = reinterpret_cast<const int32_t *>(b + kwo.at);
     D.ptab_bits = P.ptab_bits;
     D.C = P.C;
-    D.S = P.S;
     D.S_dense = P.S_dense;
     D.K = P.K;
-    D.max_len = P.max_len;
     D.hash_mul = P.hash_mul;
     return AC_OK;
 }
@@ -180,6 +194,7 @@ void fill_info(const Plan &P, ac_info_t *o) {
     o->n_prefixes = P.n_prefixes;
     o->n_windows2 = P.sampled ? P.n_windows2 : 0;
     o->n_windows4 = P.sampled4 ? P.n_windows4 : 0;
+    o->n_quads4 = P.pair4 ? P.n_quads4 : 0;
     o->dense_bytes = int64_t(P.dense.size()) * 4;
     o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
     o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;
@@ -195,7 +210,7 @@ void fill_info(const Plan &P, ac_info_t *o) {
 int check_launch(const ac_launch *l) {
     if (!l) return AC_OK;
     if (l->policy < AC_POLICY_AUTO || l->policy > AC_POLICY_DIRECT) return fail(AC_EINVAL, "ac_launch: bad policy");
-    if (l->filter < AC_FILTER_AUTO || l->filter > AC_FILTER_DUAL19) return fail(AC_EINVAL, "ac_launch: bad filter");
+    if (l->filter < AC_FILTER_AUTO || l->filter > AC_FILTER_PAIR20) return fail(AC_EINVAL, "ac_launch: bad filter");
     if (l->block != 0 && l->block != 256 && l->block != 512 && l->block != 1024)
         return fail(AC_EINVAL, "ac_launch: block must be 256, 512 or 1024");
     if (l->segs != 0 && l->segs != 1 && l->segs != 2 && l->segs != 4)
@@ -267,7 +282,7 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
     if (batch && launch && launch->policy == AC_POLICY_DIRECT) return fail(AC_ENOTSUP, "batches use the filtered policy");
     const ac_launch cfg = resolved(a, S, launch, batch);
     CountSlot *slot = nullptr;
-    int rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg));
+    int rc = slot_for(a, stream, &slot);
     if (rc) return rc;
     const bool timed = launch && (launch->flags & AC_LAUNCH_TIME_SCAN) && S.n > 0;
     g_scan_ms = g_stream_ms = g_walk_ms = -1.0f;
@@ -414,12 +429,25 @@ int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const 
 
 int pfac::report_error(int code, const std::string &msg) { return fail(code, msg); }
 
-int pfac::reserve_stream_scratch(hipStream_t stream, int64_t regions) {
-    int dev = 0;
+int pfac::reserve_stream_scratch(hipStream_t stream) {
+    int dev = 0, cus = 1;
+    int64_t lds_block = 0, lds_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    int rc = device_props(dev, &cus, &lds_block, &lds_cu);
+    if (rc) return rc;
     CountSlot *slot = nullptr;
-    return count_slot(dev, stream, &slot, regions);
+    return count_slot(dev, stream, &slot, widest_scan_regions(cus, lds_cu));
+}
+
+void pfac::release_stream_scratch(hipStream_t stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_slots_mu);
+    auto it = g_slots.find(std::make_pair(dev, stream));
+    if (it == g_slots.end()) return;
+    free_slot(it->second);
+    g_slots.erase(it);
 }
 
 extern "C" {
@@ -505,7 +533,7 @@ int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t str
     std::vector<ac_launch> cands;
     for (int stride : {1, 2, 4}) {
         if ((stride == 2 && !P.sampled) || (stride == 4 && !P.sampled4)) continue;
-        for (int filter = AC_FILTER_BYTES17; filter <= AC_FILTER_DUAL19; ++filter)
+        for (int filter = AC_FILTER_BYTES17; filter <= AC_FILTER_PAIR20; ++filter)
             for (int segs : {1, 2, 4}) {
                 ac_launch c{};
                 c.policy = AC_POLICY_FILTERED;
@@ -530,7 +558,7 @@ int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t str
         bool ok = true;
         for (int rep = 0; rep < 3 && ok; ++rep) {
             CountSlot *slot = nullptr;
-            if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) { ok = false; break; }
+            if ((rc = slot_for(a, stream, &slot))) { ok = false; break; }
             KernelTiming T;
             T.scan0 = e0;
             T.scan1 = e1;
@@ -578,7 +606,7 @@ int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len, co
     const ScanArgs S = single_args(d_text, len, matches);
     const ac_launch cfg = resolved(a, S, launch, false);
     CountSlot *slot = nullptr;
-    if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    if ((rc = slot_for(a, stream, &slot))) return rc;
     return enqueue(a, S, cfg, false, true, reinterpret_cast<unsigned long long *>(d_count), slot->hs, stream);
 }
 
@@ -603,7 +631,7 @@ int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts, const in
     const ScanArgs S = batch_args(d_texts, d_text_offsets, n_texts, total_bytes, matches);
     const ac_launch cfg = resolved(a, S, launch, true);
     CountSlot *slot = nullptr;
-    if ((rc = count_slot(a->device, stream, &slot, scan_regions(a, S.text, S.n, cfg)))) return rc;
+    if ((rc = slot_for(a, stream, &slot))) return rc;
     return enqueue(a, S, cfg, true, true, reinterpret_cast<unsigned long long *>(d_count), slot->hs, stream);
 }
 

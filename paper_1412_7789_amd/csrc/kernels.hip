@@ -39,18 +39,20 @@ namespace {
 
 constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
 constexpr int kDrain = 64;       // candidates taken per drain (1 per lane; 128 and 192 measured slower)
+// A queue holds fewer than kDrain entries before a push round and gains at
+// most one per lane in it, so its last entries are never used by the queue:
+// the last dword of the first wave's queue holds the block's slot counter.
+static_assert(2 * kDrain <= kQueueCap - 4, "queue room");
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
+// AC_FILTER_PAIR20 is the default (for texts of 16 MiB and more) up to this
+// many 4-byte windows: two bits per key fill about 2 keys / 2^15 of the map
+constexpr int32_t kPairMaxKeys = 12000;
+// (queue entry, keyword id) pairs a wave's queue holds as its match stage,
+// after its count and before the slot counter
+constexpr int kWaveStageCap = (kQueueCap - 4) / 2;
 
 __device__ __forceinline__ int imin(int a, int b) { return a < b ? a : b; }
 
-// Minimum of v over the wave's lanes.
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint32_t o = uint32_t(__shfl_xor(int(v), d));
-        v = o < v ? o : v;
-    }
-    return v;
-}
 __device__ __forceinline__ int64_t lmin(int64_t a, int64_t b) { return a < b ? a : b; }
 __device__ __forceinline__ int64_t lmax(int64_t a, int64_t b) { return a > b ? a : b; }
 
@@ -340,21 +342,16 @@ __device__ __forceinline__ bool equal_bytes(const uint8_t *t, const uint8_t *k, 
 // the exact prefix table gave e = {state at depth K | final bit}: further
 // transitions come from the transition table, and once the remaining path is
 // forced (a unary chain to a leaf with no keyword ending in between) the
-// leaf's keyword is compared with the text directly.  With REC, rb holds the
-// 8 text bytes that follow the prefix (as captured by the streaming kernel),
-// so most walks end without reading the text again.  Emits every keyword
-// starting at o.
-template <bool REC, bool STAGED>
-__device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, const uint8_t *cls, int64_t o,
-                                          uint32_t e, uint2 rb, MatchStage *st, const uint32_t *loff = nullptr) {
-    auto out = [&](int64_t off, int32_t tid, int32_t state) __attribute__((always_inline)) {
-        if (STAGED) emit_staged(A, S, st, off, tid, state);
-        else emit(A, S, off, tid, state);
-    };
+// leaf's keyword is compared with the text directly.  The walk never reads
+// at or past `end` (the end of o's text).  With REC, rb holds the 8 text
+// bytes that follow the prefix (as captured by the streaming kernel), so most
+// walks end without reading the text again.  Every keyword starting at o is
+// reported, through ids(state) for all keyword ids of a final state or
+// one(pid) for a single id.
+template <bool REC, typename Ids, typename One>
+__device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, int64_t o, int64_t end, uint32_t e,
+                                          uint2 rb, Ids &&ids, One &&one) {
     const int K = A.K;
-    int64_t tstart, end;
-    int32_t tid;
-    locate_text(S, loff, o, tstart, end, tid);
     if (o + K > end) return;          // the prefix ran into the next text of a batch
     auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
         if (REC) {
@@ -366,7 +363,7 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
     };
     int32_t s = int32_t(e & kStateMask);
     int64_t d = K;
-    if (e >> 31) out(o - tstart, tid, s);
+    if (e >> 31) ids(s);
     while (true) {
         const int4 ti = A.tailinfo[s];
         if (ti.x >= 0) {
@@ -374,17 +371,17 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, co
             const int64_t L = d + ti.z;
             if (o + L > end) return;
             if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
-            if (ti.w > 0) emit_one(S, STAGED ? st : nullptr, o - tstart, tid, ti.w - 1);
-            else out(o - tstart, tid, ti.x);
+            if (ti.w > 0) one(ti.w - 1);
+            else ids(ti.x);
             return;
         }
         if (ti.x == -2) return;        // a leaf: nothing below
         if (o + d >= end) return;
-        const int32_t e2 = step_global(A, cls, s, byte_at(o + d));
+        const int32_t e2 = step_global(A, A.cls, s, byte_at(o + d));
         if (e2 == 0) return;
         s = e2 & 0x7fffffff;
         ++d;
-        if (e2 < 0) out(o - tstart, tid, s);
+        if (e2 < 0) ids(s);
     }
 }
 
@@ -394,10 +391,29 @@ struct FilterLaunch {
     int64_t V;               // mis + n: end of the text in `base` coordinates
     int64_t n_chunks;        // ceil(V / chunk bytes)
     int64_t c_lo, c_hi;      // interior chunks [c_lo, c_hi): whole chunk + 16 B inside the text
-    int32_t filter_kind;
+    const uint8_t *filter;   // the filter map this launch stages in LDS
     int32_t hit_cap;         // entries per wave region
-    uint4 *hits;             // [waves * hit_cap]: {chunk step << 12 | position, prefix-table value,
+    uint4 *hits;             // [waves * hit_cap]: {slot << 12 | position, prefix-table value,
                              //  the 8 text bytes after the prefix}
+};
+
+// The filtered kernel's one argument.
+struct KArgs {
+    DevAut A;
+    ScanArgs S;
+    FilterLaunch F;
+};
+typedef const __attribute__((address_space(4))) KArgs *KArgsPtr;
+
+// Slot -> interior chunk of one block (see filtered_kernel).
+struct SlotMap {
+    int64_t bfirst;    // the block's first chunk
+    int64_t nw;        // waves in the grid
+    uint32_t wmask;    // waves per block - 1 (a power of two minus one)
+    int32_t wlog;      // log2(waves per block)
+    __device__ __forceinline__ int64_t chunk(uint32_t slot) const {
+        return bfirst + int64_t(slot & wmask) + int64_t(slot >> wlog) * nw;
+    }
 };
 
 template <int SEGS>
@@ -440,15 +456,33 @@ __device__ __forceinline__ void load_partial(const FilterLaunch &F, int64_t c, u
     R.tail = get4((c + 1) * CH);
 }
 
-// Candidate mask of one chunk: bit 16 j + s is set when the K bytes at offset
-// s of the lane's 16 bytes in segment j hash to a set filter entry (stride
-// 1), or when the 3 bytes at the odd offset of s's pair do (stride 2).
-template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL>
+// Candidate mask of one chunk: bit 16 j + s is set when offset s of the
+// lane's 16 bytes in segment j may start a keyword.
+//
+// Stride 1: the K bytes at offset s hash to a set filter entry.
+// Stride 2 and 4: only the 3-byte windows starting at s = STRIDE, 2 STRIDE,
+// ..., 16 are tested (s = 16 is the next lane's first bytes), against the
+// keywords' windows at positions 1 .. STRIDE; a keyword starting at o has its
+// window at position s - o tested for the one sampled s in o + 1 .. o +
+// STRIDE, so a positive makes the STRIDE offsets s - STRIDE .. s - 1
+// candidates.  Windows at s = 4, 8, 12, 16 are whole registers (the hash
+// reads 24 bits), so stride 4 extracts no bytes and stride 2 half as many.
+// A bit map is tested without shifting the looked-up bit into place: the
+// hash is p = x * mul + c with c = -b mod 32 for destination bit b, so
+// rotating the word right by p (mod 32) moves the key's bit (x * mul) mod 32
+// to b.  Adding c may carry into the word index; the host sets each key's
+// bit in both words that can result.
+// PAIR (stride 4): the window at s is the whole register d[s / 4], four
+// bytes, tested against the keywords' 4-byte windows at positions 1 .. 4:
+// its first three bytes pick the word, and the bits (x * mul) mod 32 and
+// (byte 3) mod 32 of that word must both be set.
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL, bool PAIR>
 __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
                                                            const uint8_t *sfilt, uint32_t mul) {
     constexpr uint32_t kmask = K >= 3 ? 0xFFFFFFu : ((1u << (8 * K)) - 1u);
     // byte map: 2^FLOG2 entries; bit map: 2^(FLOG2-2) words of 32 bits
     constexpr int shift = BITMAP ? 32 - (FLOG2 - 2) : 32 - FLOG2;
+    const uint32_t *fm = reinterpret_cast<const uint32_t *>(sfilt);
     uint32_t mseg[SEGS];
 #pragma unroll
     for (int j = 0; j < SEGS; ++j) {
@@ -459,29 +493,59 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
                                                       : R.tail;
         d[4] = lane == 63 ? from_next_seg : from_next_lane;
         uint32_t mj = 0;
+        if (STRIDE == 1) {
 #pragma unroll
-        for (int s = STRIDE - 1; s < 16; s += STRIDE) {
-            const int w = s >> 2, r = s & 3;
-            uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
-            if (K < 3) x &= kmask;
-            const uint32_t p = hash24(x, mul);
-            uint32_t v;
-            if (DUAL) {
-                // two maps of 2^(FLOG2 - 3) words, independent hashes: both bits must be set
-                const uint32_t p2 = hash24(x, kFilterMul2);
-                const uint32_t *fm = reinterpret_cast<const uint32_t *>(sfilt);
-                v = __builtin_amdgcn_ubfe(fm[p >> (shift + 1)], p, 1u) &
-                    __builtin_amdgcn_ubfe(fm[(1u << (FLOG2 - 3)) + (p2 >> (shift + 1))], p2, 1u);
-            } else if (BITMAP) {
-                v = __builtin_amdgcn_ubfe(reinterpret_cast<const uint32_t *>(sfilt)[p >> shift], p, 1u);
-            } else {
-                v = sfilt[p >> shift];
+            for (int s = 0; s < 16; ++s) {
+                const int w = s >> 2, r = s & 3;
+                uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
+                if (K < 3) x &= kmask;
+                const uint32_t p = hash24(x, mul);
+                uint32_t v;
+                if (DUAL) {
+                    const uint32_t p2 = hash24(x, kFilterMul2);
+                    v = __builtin_amdgcn_ubfe(fm[p >> (shift + 1)], p, 1u) &
+                        __builtin_amdgcn_ubfe(fm[(1u << (FLOG2 - 3)) + (p2 >> (shift + 1))], p2, 1u);
+                } else if (BITMAP) {
+                    v = __builtin_amdgcn_ubfe(fm[p >> shift], p, 1u);
+                } else {
+                    v = sfilt[p >> shift];
+                }
+                mj |= v << s;
             }
-            mj |= v << s;
+        } else {
+#pragma unroll
+            for (int s = STRIDE; s <= 16; s += STRIDE) {
+                const int w = s >> 2, r = s & 3;
+                const uint32_t x = r == 0 ? d[w] : __builtin_amdgcn_alignbyte(d[w + 1], d[w], uint32_t(r));
+                const int b = s - STRIDE;                 // destination bit
+                const uint32_t c = uint32_t(32 - b) & 31u;
+                const uint32_t p = hash24(x, mul) + c;
+                if (PAIR) {
+                    const uint32_t p0 = hash24(x, mul);
+                    const uint32_t w1 = fm[p0 >> shift];
+                    const uint32_t v = __builtin_amdgcn_alignbit(w1, w1, p0) & __builtin_amdgcn_alignbit(w1, w1, x >> 24);
+                    mj |= (v & 1u) << b;
+                } else if (BITMAP) {
+                    uint32_t v;
+                    if (DUAL) {
+                        // two maps of 2^(FLOG2 - 3) words, independent hashes: both bits must be set
+                        const uint32_t p2 = hash24(x, kFilterMul2) + c;
+                        const uint32_t w1 = fm[p >> (shift + 1)];
+                        const uint32_t w2 = fm[(1u << (FLOG2 - 3)) + (p2 >> (shift + 1))];
+                        v = __builtin_amdgcn_alignbit(w1, w1, p) & __builtin_amdgcn_alignbit(w2, w2, p2);
+                    } else {
+                        const uint32_t w1 = fm[p >> shift];
+                        v = __builtin_amdgcn_alignbit(w1, w1, p);
+                    }
+                    mj = (v & (1u << b)) | (mj & ~(1u << b));
+                } else {
+                    mj |= uint32_t(sfilt[p >> shift]) << b;
+                }
+            }
+            // a positive at bit b covers the offsets b .. b + STRIDE - 1
+            if (STRIDE == 2) mj |= mj << 1;
+            if (STRIDE == 4) mj = __umul24(mj, 15u);
         }
-        // a window tested at s covers the offsets s - STRIDE + 1 .. s
-        if (STRIDE == 2) mj |= mj >> 1;
-        if (STRIDE == 4) mj |= (mj >> 1) | (mj >> 2) | (mj >> 3);
         mseg[j] = mj;
     }
     // bit 16 j + s: segment j, byte s
@@ -490,261 +554,406 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
-// Streaming kernel of the filtered policy.  Candidate offsets wait in a
-// per-wave LDS queue; a drain takes kDrain of them at once (each lane loads
-// the prefix window of kDrain / 64 candidates with independent loads, then
-// looks the prefix up in the exact prefix table) and appends the surviving
-// prefixes, with the 8 text bytes after them, to the wave's hit region with
-// plain stores.  The chunk loop has no walk, atomic, call or other dependent
-// global access.  Hits that do not fit the region are not stored: the region
-// records the first chunk step that lost one, and a post-pass after the loop
-// re-filters the wave's chunks from that step on (and the partial chunks at
-// the text's ends) and walks their hits itself.  Finally the block walks the
-// stored hits of its waves.
-template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL>
-__global__ __launch_bounds__(1024) void filtered_kernel(const DevAut A, const ScanArgs S, const FilterLaunch F) {
+// The kernel's argument block, read where it lies.  The empty asm hides the
+// pointer's origin from the compiler, so the fields read through it are
+// loaded here and not all at the kernel's entry, from where they would stay
+// live (and spill) across the streaming loop.
+__device__ __forceinline__ const KArgs *kernel_args() {
+    KArgsPtr p = (KArgsPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return (const KArgs *)p;   // still known to be constant memory: read with scalar loads
+}
+
+// Exact prefix lookup through the LDS copy of the prefix table when it has
+// one, else through global memory.
+__device__ __forceinline__ uint2 probe_prefix(bool in_lds, const uint32_t *sptab, const uint32_t *gptab, int bits,
+                                              uint32_t x, uint32_t mul) {
+    if (in_lds)
+        return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
+            lo = reinterpret_cast<const u32x4 *>(sptab)[2 * b];
+            hi = reinterpret_cast<const u32x4 *>(sptab)[2 * b + 1];
+        }, bits, x, mul);
+    return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
+        lo = gload16(reinterpret_cast<const uint8_t *>(gptab + 8 * b));
+        hi = gload16(reinterpret_cast<const uint8_t *>(gptab + 8 * b + 4));
+    }, bits, x, mul);
+}
+
+// Streaming kernel of the filtered policy.
+//
+// Work is dealt out in slots: slot i of block b is interior chunk c_lo + b W
+// + (i mod W) + (i div W) nw (W waves per block, nw waves in the grid, so a
+// step of the grid still reads one contiguous stretch of text).  Each wave
+// starts with slots `wave` and `wave + W` and takes every further slot from
+// a counter in LDS, one slot ahead of need.  Waves of one block progress at
+// very different rates (the SIMDs favour older waves), and with a fixed
+// share per wave the block would wait for its slowest one.
+//
+// Candidate offsets wait in a per-wave LDS queue; a drain takes kDrain of
+// them at once (each lane loads the prefix window of kDrain / 64 candidates
+// with independent loads, then looks the prefix up in the exact prefix table)
+// and appends the surviving prefixes, with the 8 text bytes after them, to
+// the wave's hit region with plain stores.  The chunk loop has no walk,
+// atomic in global memory, call or other dependent global access.  A wave
+// whose region has no room for another drain leaves the loop and goes on in
+// a slow mode: it scans the rest of its slots one chunk at a time and walks
+// every hit as soon as the prefix table confirms it.  So does every wave with
+// the partial chunks at the text's ends.  Finally each wave (one text) or the
+// whole block (a batch) walks the stored hits.
+template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL, bool PAIR>
+__global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
     constexpr int PT_SLOTS = FLOG2 >= 17 ? 2048 : 8192;   // prefix-table slots that fit beside the filter
     __shared__ __align__(16) uint32_t sptab[2 * PT_SLOTS];
-    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
-    if (pt_lds) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.ptab);
-        uint4 *dst = reinterpret_cast<uint4 *>(sptab);
-        for (int i = threadIdx.x; i < (2 << A.ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
-    }
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(A.filter[stride_set(STRIDE) * kNumFilterKinds + F.filter_kind - 1]);
-        uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
-        for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
-    }
-    __syncthreads();
-
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
     constexpr int PER_LANE = kDrain / kWave;
+    const int waves_per_block = int(blockDim.x) / kWave;
+    const int wlog = __builtin_ctz(unsigned(waves_per_block));   // W is a power of two
     const unsigned lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
-    const int waves_per_block = int(blockDim.x) / kWave;
     uint32_t *q = squeue + wave * kQueueCap;
     const int64_t w = int64_t(blockIdx.x) * waves_per_block + wave;
     const int64_t nw = int64_t(gridDim.x) * waves_per_block;
-    const uint32_t mul = A.hash_mul;
-    uint4 *hits = F.hits + w * F.hit_cap;
+    uint32_t &snext = squeue[kQueueCap - 1];              // next slot to hand out
     int hcount = 0;                    // hits stored in this wave's region
-    uint32_t kmin = 0xFFFFFFFFu;       // first chunk step that lost a hit
-
-    // Queue entry = (k << 12) | position in chunk, for chunk qbase + k * qstride.
-    int64_t qbase = F.c_lo + w, qstride = nw;
     int qlen = 0;
 
-    auto probe = [&](uint32_t x) __attribute__((always_inline)) -> uint2 {
-        if (pt_lds)
-            return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
-                lo = reinterpret_cast<const u32x4 *>(sptab)[2 * b];
-                hi = reinterpret_cast<const u32x4 *>(sptab)[2 * b + 1];
-            }, A.ptab_bits, x, mul);
-        return prefix_state([&](uint32_t b, u32x4 &lo, u32x4 &hi) {
-            lo = gload16(reinterpret_cast<const uint8_t *>(A.ptab + 8 * b));
-            hi = gload16(reinterpret_cast<const uint8_t *>(A.ptab + 8 * b + 4));
-        }, A.ptab_bits, x, mul);
-    };
-    auto offset_of = [&](uint32_t ent) __attribute__((always_inline)) {
-        return (qbase + int64_t(ent >> 12) * qstride) * CH + int64_t(ent & 4095u) - F.mis;
-    };
-
-    // Streaming-loop drain of the newest `take` entries (interior chunks only:
-    // there o + 16 <= n, so the aligned 16 bytes from (o & ~3) lie in the text
-    // and give the prefix and the 8 bytes after it).
-    auto drain_store = [&](int take) __attribute__((always_inline)) {
-        wave_sync();
-        uint32_t ent[PER_LANE];
-#pragma unroll
-        for (int r = 0; r < PER_LANE; ++r) {
-            // lanes past `take` repeat the first entry, so every load below is valid
-            const int i = int(lane) + r * kWave;
-            ent[r] = q[qlen - take + (i < take ? i : 0)];
-        }
-        wave_sync();
-        qlen -= take;
-        u32x4 win[PER_LANE];
-        uint32_t sh[PER_LANE];
-#pragma unroll
-        for (int r = 0; r < PER_LANE; ++r) {
-            const uintptr_t a = reinterpret_cast<uintptr_t>(S.text + offset_of(ent[r]));
-            sh[r] = uint32_t(a & 3u);
-            const uint8_t *pa = reinterpret_cast<const uint8_t *>(a & ~uintptr_t(3));
-            win[r].x = gload4(pa);
-            win[r].y = gload4(pa + 4);
-            win[r].z = gload4(pa + 8);
-            win[r].w = gload4(pa + 12);
-        }
-#pragma unroll
-        for (int r = 0; r < PER_LANE; ++r) {
-            const uint32_t y0 = __builtin_amdgcn_alignbyte(win[r].y, win[r].x, sh[r]);
-            const uint32_t y1 = __builtin_amdgcn_alignbyte(win[r].z, win[r].y, sh[r]);
-            const uint32_t y2 = __builtin_amdgcn_alignbyte(win[r].w, win[r].z, sh[r]);
-            const uint32_t x = K >= 3 ? (y0 & 0xFFFFFFu) : (y0 & ((1u << (8 * K)) - 1u));
-            const uint32_t rb0 = __builtin_amdgcn_alignbyte(y1, y0, uint32_t(K));
-            const uint32_t rb1 = __builtin_amdgcn_alignbyte(y2, y1, uint32_t(K));
-            uint32_t e = 0;
-            if (int(lane) + r * kWave < take) {
-                const uint2 kv = probe(x);
-                e = kv.y;
-                // a non-final prefix state whose only child's byte differs from
-                // the text's next byte ends the walk at the prefix
-                if ((e & kHasNext) && !(e >> 31) && (kv.x >> 24) != (rb0 & 0xFFu)) e = 0u;
-            }
-            const unsigned long long hit = __ballot(e != 0u);
-            if (hit == 0) continue;
-            const int slot = hcount + int(rank_in(hit));
-            if (e != 0u) {
-                if (slot < F.hit_cap) gstore16(hits + slot, ent[r], e, rb0, rb1);
-                else kmin = min(kmin, ent[r] >> 12);
-            }
-            hcount = imin(hcount + __popcll(hit), F.hit_cap);
-        }
-    };
-    // Post-pass drain: probes with byte loads and walks the hits right here.
-    auto drain_walk = [&](int take) __attribute__((always_inline)) {
-        wave_sync();
-        uint32_t ent[PER_LANE];
-#pragma unroll
-        for (int r = 0; r < PER_LANE; ++r) {
-            const int i = int(lane) + r * kWave;
-            ent[r] = q[qlen - take + (i < take ? i : 0)];
-        }
-        wave_sync();
-        qlen -= take;
-        for (int r = 0; r < PER_LANE; ++r) {
-            if (int(lane) + r * kWave >= take) continue;
-            const int64_t o = offset_of(ent[r]);
-            uint32_t x = 0;
-            for (int j = 0; j < K; ++j) x |= gload1(S.text + o + j) << (8 * j);
-            const uint2 kv = probe(x);
-            if (kv.y) walk_rest<false, false>(A, S, A.cls, o, kv.y, make_uint2(0u, 0u), nullptr);
-        }
-    };
-    auto push = [&](unsigned long long m, uint32_t k, auto &&drain) __attribute__((always_inline)) {
+    // Queues the candidate offsets of mask m (chunk slot k), draining the
+    // queue whenever it holds kDrain entries.  Returns false, leaving the
+    // bits not yet queued in m, if `drain` refuses to run.
+    auto push = [&](unsigned long long &m, uint32_t k, auto &&drain) __attribute__((always_inline)) {
         while (true) {
+            if (qlen >= kDrain && !drain(kDrain)) return false;
             const unsigned long long act = __ballot(m != 0);
-            if (act == 0) break;
+            if (act == 0) return true;
             if (m) {
                 const int b = __ffsll(static_cast<long long>(m)) - 1;
                 q[qlen + int(rank_in(act))] = (k << 12) | uint32_t((b >> 4) * kSegBytes + int(lane) * 16 + (b & 15));
                 m &= m - 1;
             }
             qlen += __popcll(act);
-            if (qlen >= kDrain) drain(kDrain);
         }
     };
+    // The newest `take` queue entries, one per lane (lanes past `take`
+    // repeat the first one, so every load made from them is valid).
+    auto pop = [&](int take, uint32_t (&ent)[PER_LANE]) __attribute__((always_inline)) {
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < PER_LANE; ++r) {
+            const int i = int(lane) + r * kWave;
+            ent[r] = q[qlen - take + (i < take ? i : 0)];
+        }
+        wave_sync();
+        qlen -= take;
+    };
 
-    // interior chunks, two register sets in turn so that the next chunk's
-    // loads are in flight while this one is filtered
+    // Where the streaming loop stopped: every slot from `cur` on is left to
+    // the slow mode (none if cur_ok is false), cur's candidates not yet
+    // queued in `rest`, and lane 0's `ahead` holding the slot after nxt.
+    bool slow = false;
+    bool cur_ok = false;
+    uint32_t cur = 0, nxt = 0, ahead = 0;
+    unsigned long long rest = 0;
+
+    // ---- set-up and streaming: the fields they read, and no others ----
     {
-        // The next chunk's loads are issued unconditionally (the last step
-        // reloads its own chunk): with a fixed number of loads between a
-        // chunk's loads and its first use, the compiler waits for that chunk
-        // only, and the loads stay in flight while the current one is filtered.
-        ChunkRegs<SEGS> ra, rb;
-        int64_t c = F.c_lo + w;
-        uint32_t k = 0;
-        if (c < F.c_hi) load_interior<SEGS>(F, c, lane, ra);
-        while (c < F.c_hi) {
-            const int64_t c1 = c + nw;
-            load_interior<SEGS>(F, c1 < F.c_hi ? c1 : c, lane, rb);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(ra, lane, sfilt, mul), k++, drain_store);
-            c = c1;
-            if (c >= F.c_hi) break;
-            const int64_t c2 = c + nw;
-            load_interior<SEGS>(F, c2 < F.c_hi ? c2 : c, lane, ra);
-            push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(rb, lane, sfilt, mul), k++, drain_store);
-            c = c2;
+        const KArgs *P1 = kernel_args();
+        const FilterLaunch F = P1->F;
+        const uint8_t *text = P1->S.text;
+        const uint32_t *gptab = P1->A.ptab;
+        const int ptab_bits = P1->A.ptab_bits;
+        const uint32_t mul = P1->A.hash_mul;
+        const bool pt_lds = ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
+        if (pt_lds) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(gptab);
+            uint4 *dst = reinterpret_cast<uint4 *>(sptab);
+            for (int i = threadIdx.x; i < (2 << ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
         }
-        while (qlen > 0) drain_store(imin(qlen, kDrain));
-    }
-    kmin = __builtin_amdgcn_readfirstlane(wave_min(kmin));
-
-    // post-pass 1: interior chunks from the first step that lost a hit
-    for (uint32_t k = kmin; kmin != 0xFFFFFFFFu; ++k) {
-        const int64_t c = F.c_lo + w + int64_t(k) * nw;
-        if (c >= F.c_hi) break;
-        ChunkRegs<SEGS> r;
-        load_interior<SEGS>(F, c, lane, r);
-        push(filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(r, lane, sfilt, mul), k, drain_walk);
-        while (qlen > 0) drain_walk(imin(qlen, kDrain));
-    }
-    // post-pass 2: chunks overlapping an end of the text: [0, p0) and [p1, n_chunks)
-    const int64_t p0 = lmin(F.c_lo, F.n_chunks);
-    const int64_t p1 = lmax(F.c_hi, F.c_lo);
-    const int64_t n_partial = p0 + (F.n_chunks - p1);
-    for (int64_t i = w; i < n_partial; i += nw) {
-        const int64_t pc = i < p0 ? i : p1 + (i - p0);
-        ChunkRegs<SEGS> r;
-        load_partial<SEGS>(F, pc, lane, r);
-        unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL>(r, lane, sfilt, mul);
-        for (int b = 0; b < SEGS * 16; ++b) {
-            // keep offsets o with 0 <= o and o + K <= n
-            const int64_t o = pc * CH + (b >> 4) * kSegBytes + int64_t(lane) * 16 + (b & 15) - F.mis;
-            if (o < 0 || o + K > S.n) m &= ~(1ull << b);
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(F.filter);
+            uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
+            for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
         }
-        qbase = pc;
-        qstride = 0;
-        push(m, 0, drain_walk);
-        while (qlen > 0) drain_walk(imin(qlen, kDrain));
-    }
-
-    // The block walks the hits its waves stored, spread over all its threads
-    // (one flat index over the waves' regions).  The filter and queues are
-    // no longer needed, so their LDS holds the match stage; the matches leave
-    // with one global atomic per block.
-    // Each wave leaves its hit count and first lost step in its own (empty)
-    // queue; after the barrier the stage, the prefix sums of the counts and
-    // the steps go where the filter was.
-    if (lane == 0) {
-        q[0] = uint32_t(hcount);
-        q[1] = kmin;
-    }
-    __syncthreads();
-    static_assert((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 <= (1u << FLOG2),
-                  "the walk's stage must fit where the filter was");
-    MatchStage *st = reinterpret_cast<MatchStage *>(sfilt);
-    int32_t *wfirst = reinterpret_cast<int32_t *>(sfilt + (sizeof(MatchStage) + 15) / 16 * 16);   // [waves + 1]
-    uint32_t *wkmin = reinterpret_cast<uint32_t *>(wfirst + kMaxWaves + 1);                        // [waves]
-    if (threadIdx.x == 0) {
-        wfirst[0] = 0;
-        for (int j = 0; j < waves_per_block; ++j) {
-            wfirst[j + 1] = wfirst[j] + int32_t(squeue[j * kQueueCap]);
-            wkmin[j] = squeue[j * kQueueCap + 1];
-        }
-        st->n = 0;
-    }
-    __syncthreads();
-    const int32_t total = wfirst[waves_per_block];
-    const int64_t r0 = int64_t(blockIdx.x) * waves_per_block;
-    // A batch's text starts (as offsets from the first text) are copied to
-    // LDS when they fit, beside the stage or where the prefix table was, so
-    // the walks look their texts up there.
-    constexpr int kStageEnd = ((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 + 15) / 16 * 16;
-    constexpr int kLdsTexts = FLOG2 >= 17 ? ((1 << FLOG2) - kStageEnd) / 4 : 2 * PT_SLOTS;
-    static_assert(kLdsTexts >= 4096, "room for the text starts of a batch of 4096 texts");
-    uint32_t *lds_off = FLOG2 >= 17 ? reinterpret_cast<uint32_t *>(sfilt + kStageEnd) : sptab;
-    const uint32_t *loff = nullptr;
-    if (S.text_off && total > 0 && S.n_texts < kLdsTexts && S.n < (int64_t(1) << 32)) {
-        const int64_t base0 = S.text_off[0];
-        for (int i = int(threadIdx.x); i <= S.n_texts; i += int(blockDim.x)) lds_off[i] = uint32_t(S.text_off[i] - base0);
+        SlotMap M;
+        M.bfirst = F.c_lo + int64_t(blockIdx.x) * waves_per_block;
+        M.nw = nw;
+        M.wmask = uint32_t(waves_per_block - 1);
+        M.wlog = wlog;
+        if (threadIdx.x == 0) snext = uint32_t(2 * waves_per_block);
         __syncthreads();
-        loff = lds_off;
+
+        uint4 *hits = F.hits + w * F.hit_cap;
+        // Streaming-loop drain of the newest `take` entries (interior chunks
+        // only: there o + 16 <= n, so the aligned 16 bytes from (o & ~3) lie
+        // in the text and give the prefix and the 8 bytes after it).  Refuses
+        // when the region might not hold its hits.
+        auto drain_store = [&](int take) __attribute__((always_inline)) {
+            if (hcount + kDrain > F.hit_cap) return false;
+            uint32_t ent[PER_LANE];
+            pop(take, ent);
+            u32x4 win[PER_LANE];
+            uint32_t sh[PER_LANE];
+#pragma unroll
+            for (int r = 0; r < PER_LANE; ++r) {
+                const int64_t o = M.chunk(ent[r] >> 12) * CH + int64_t(ent[r] & 4095u) - F.mis;
+                const uintptr_t a = reinterpret_cast<uintptr_t>(text + o);
+                sh[r] = uint32_t(a & 3u);
+                const uint8_t *pa = reinterpret_cast<const uint8_t *>(a & ~uintptr_t(3));
+                win[r].x = gload4(pa);
+                win[r].y = gload4(pa + 4);
+                win[r].z = gload4(pa + 8);
+                win[r].w = gload4(pa + 12);
+            }
+#pragma unroll
+            for (int r = 0; r < PER_LANE; ++r) {
+                const uint32_t y0 = __builtin_amdgcn_alignbyte(win[r].y, win[r].x, sh[r]);
+                const uint32_t y1 = __builtin_amdgcn_alignbyte(win[r].z, win[r].y, sh[r]);
+                const uint32_t y2 = __builtin_amdgcn_alignbyte(win[r].w, win[r].z, sh[r]);
+                const uint32_t x = K >= 3 ? (y0 & 0xFFFFFFu) : (y0 & ((1u << (8 * K)) - 1u));
+                const uint32_t rb0 = __builtin_amdgcn_alignbyte(y1, y0, uint32_t(K));
+                const uint32_t rb1 = __builtin_amdgcn_alignbyte(y2, y1, uint32_t(K));
+                uint32_t e = 0;
+                if (int(lane) + r * kWave < take) {
+                    const uint2 kv = probe_prefix(pt_lds, sptab, gptab, ptab_bits, x, mul);
+                    e = kv.y;
+                    // a non-final prefix state whose only child's byte differs
+                    // from the text's next byte ends the walk at the prefix
+                    if ((e & kHasNext) && !(e >> 31) && (kv.x >> 24) != (rb0 & 0xFFu)) e = 0u;
+                }
+                const unsigned long long hit = __ballot(e != 0u);
+                if (hit == 0) continue;
+                if (e != 0u) gstore16(hits + hcount + int(rank_in(hit)), ent[r], e, rb0, rb1);
+                hcount += __popcll(hit);
+            }
+            return true;
+        };
+
+        // Interior chunks, two register sets in turn so that the next chunk's
+        // loads are in flight while this one is filtered.  The next chunk's
+        // loads are issued unconditionally (the last step reloads its own
+        // chunk): with a fixed number of loads between a chunk's loads and
+        // its first use, the compiler waits for that chunk only.
+        ChunkRegs<SEGS> ra, rb;
+        cur = uint32_t(wave);
+        nxt = uint32_t(wave + waves_per_block);
+        if (lane == 0) ahead = atomicAdd(&snext, 1u);
+        cur_ok = M.chunk(cur) < F.c_hi;
+        if (cur_ok) load_interior<SEGS>(F, M.chunk(cur), lane, ra);
+        auto advance = [&]() __attribute__((always_inline)) {
+            // slots held by a wave only grow, and so do their chunks: once
+            // one is past the end, so is every later one
+            cur = nxt;
+            cur_ok = M.chunk(cur) < F.c_hi;
+            nxt = __builtin_amdgcn_readfirstlane(ahead);
+            if (lane == 0 && cur_ok) ahead = atomicAdd(&snext, 1u);
+        };
+        while (cur_ok) {
+            const bool nxt_ok = M.chunk(nxt) < F.c_hi;
+            load_interior<SEGS>(F, M.chunk(nxt_ok ? nxt : cur), lane, rb);
+            rest = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(ra, lane, sfilt, mul);
+            if (!push(rest, cur, drain_store)) { slow = true; break; }
+            advance();
+            if (!cur_ok) break;
+            const bool nxt_ok2 = M.chunk(nxt) < F.c_hi;
+            load_interior<SEGS>(F, M.chunk(nxt_ok2 ? nxt : cur), lane, ra);
+            rest = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(rb, lane, sfilt, mul);
+            if (!push(rest, cur, drain_store)) { slow = true; break; }
+            advance();
+        }
+        while (!slow && qlen > 0)
+            if (!drain_store(imin(qlen, kDrain))) slow = true;
     }
-    for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
-        int j = 0;
-        while (wfirst[j + 1] <= i) ++j;          // wave (region) of flat index i
-        const uint4 rec = F.hits[(r0 + j) * F.hit_cap + (i - wfirst[j])];
-        if ((rec.x >> 12) >= wkmin[j]) continue;   // walked by that wave's post-pass
-        const int64_t chunk = F.c_lo + r0 + j + int64_t(rec.x >> 12) * nw;
-        const int64_t o = chunk * CH + int64_t(rec.x & 4095u) - F.mis;
-        walk_rest<true, true>(A, S, A.cls, o, rec.y, make_uint2(rec.z, rec.w), st, loff);
+
+    // ---- slow mode, partial chunks, walks and output ----
+    const KArgs *P2 = kernel_args();
+    const DevAut A = P2->A;
+    const ScanArgs S = P2->S;
+    const FilterLaunch F = P2->F;
+    SlotMap M;
+    M.bfirst = F.c_lo + int64_t(blockIdx.x) * waves_per_block;
+    M.nw = nw;
+    M.wmask = uint32_t(waves_per_block - 1);
+    M.wlog = wlog;
+    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
+    const uint32_t mul = A.hash_mul;
+    uint4 *hits = F.hits + w * F.hit_cap;
+    auto offset_of = [&](uint32_t ent) __attribute__((always_inline)) {
+        return M.chunk(ent >> 12) * CH + int64_t(ent & 4095u) - F.mis;
+    };
+
+    {
+        int64_t pchunk = -1;         // a partial chunk's number, else -1 (entries hold slots)
+        // Drain that probes with byte loads and walks the hits right here.
+        auto drain_walk = [&](int take) __attribute__((always_inline)) {
+            uint32_t ent[PER_LANE];
+            pop(take, ent);
+            for (int r = 0; r < PER_LANE; ++r) {
+                if (int(lane) + r * kWave >= take) continue;
+                const int64_t o = (pchunk >= 0 ? pchunk : M.chunk(ent[r] >> 12)) * CH + int64_t(ent[r] & 4095u) - F.mis;
+                uint32_t x = 0;
+                for (int j = 0; j < K; ++j) x |= gload1(S.text + o + j) << (8 * j);
+                const uint2 kv = probe_prefix(pt_lds, sptab, A.ptab, A.ptab_bits, x, mul);
+                if (kv.y == 0u) continue;
+                int64_t tstart, end;
+                int32_t tid;
+                locate_text(S, nullptr, o, tstart, end, tid);
+                walk_rest<false>(A, S, o, end, kv.y, make_uint2(0u, 0u),
+                                 [&](int32_t st) { emit(A, S, o - tstart, tid, st); },
+                                 [&](int32_t pid) { emit_one(S, nullptr, o - tstart, tid, pid); });
+            }
+            return true;
+        };
+        if (slow) {
+            // the rest of cur's candidates, then cur's successors, one chunk
+            // at a time
+            (void)push(rest, cur, drain_walk);
+            uint32_t sl = nxt;
+            uint32_t after = __builtin_amdgcn_readfirstlane(ahead);
+            bool ok = cur_ok && M.chunk(sl) < F.c_hi;
+            while (ok) {
+                ChunkRegs<SEGS> r;
+                load_interior<SEGS>(F, M.chunk(sl), lane, r);
+                unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(r, lane, sfilt, mul);
+                (void)push(m, sl, drain_walk);
+                sl = after;
+                ok = M.chunk(sl) < F.c_hi;
+                if (ok) {
+                    uint32_t t = 0;
+                    if (lane == 0) t = atomicAdd(&snext, 1u);
+                    after = __builtin_amdgcn_readfirstlane(t);
+                }
+            }
+            while (qlen > 0) drain_walk(imin(qlen, kDrain));
+        }
+        // chunks overlapping an end of the text, [0, p0) and [p1, n_chunks),
+        // filtered with byte loads
+        const int64_t p0 = lmin(F.c_lo, F.n_chunks);
+        const int64_t p1 = lmax(F.c_hi, F.c_lo);
+        const int64_t n_partial = p0 + (F.n_chunks - p1);
+        for (int64_t i = w; i < n_partial; i += nw) {
+            pchunk = i < p0 ? i : p1 + (i - p0);
+            ChunkRegs<SEGS> r;
+            load_partial<SEGS>(F, pchunk, lane, r);
+            unsigned long long m = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(r, lane, sfilt, mul);
+            for (int b = 0; b < SEGS * 16; ++b) {
+                // keep offsets o with 0 <= o and o + K <= n
+                const int64_t o = pchunk * CH + (b >> 4) * kSegBytes + int64_t(lane) * 16 + (b & 15) - F.mis;
+                if (o < 0 || o + K > S.n) m &= ~(1ull << b);
+            }
+            (void)push(m, 0, drain_walk);
+            while (qlen > 0) drain_walk(imin(qlen, kDrain));
+        }
     }
-    flush_stage(S, st);
+
+    const int64_t r0 = int64_t(blockIdx.x) * waves_per_block;
+    if (!S.text_off) {
+        // One text: the wave walks its own stored hits as soon as its
+        // streaming is done, while the block's other waves still stream.
+        // Its (now empty) queue holds the matches: q[0] counts them, then
+        // (queue entry, keyword id) pairs; the block stores them after its
+        // barrier with one global atomic.  Matches beyond the stage's room go
+        // out directly.
+        wave_sync();
+        if (lane == 0) q[0] = 0u;
+        // the hit records were stored by other lanes of this wave
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        wave_sync();
+        for (int i = int(lane); i < hcount; i += kWave) {
+            const u32x4 rec = gload16(reinterpret_cast<const uint8_t *>(hits + i));
+            const int64_t o = offset_of(rec.x);
+            auto put = [&](int32_t pid) __attribute__((always_inline)) {
+                const uint32_t at = atomicAdd(&q[0], 1u);
+                if (at < uint32_t(kWaveStageCap)) {
+                    q[2 + 2 * at] = rec.x;
+                    q[3 + 2 * at] = uint32_t(pid);
+                } else {
+                    emit_one(S, nullptr, o, 0, pid);
+                }
+            };
+            walk_rest<true>(A, S, o, S.n, rec.y, make_uint2(rec.z, rec.w),
+                            [&](int32_t st) {
+                                for (int32_t k = A.out_off[st], k1 = A.out_off[st + 1]; k < k1; ++k) put(A.out_pid[k]);
+                            },
+                            put);
+        }
+        __syncthreads();
+        // every wave's matches are staged: one atomic reserves the block's
+        // output range, the filter's LDS holds the waves' prefix sums
+        int32_t *wpre = reinterpret_cast<int32_t *>(sfilt);                                // [waves + 1]
+        unsigned long long *wbase = reinterpret_cast<unsigned long long *>(sfilt + 128);
+        if (threadIdx.x == 0) {
+            int32_t t = 0;
+            for (int j = 0; j < waves_per_block; ++j) {
+                wpre[j] = t;
+                t += imin(int32_t(squeue[j * kQueueCap]), kWaveStageCap);
+            }
+            wpre[waves_per_block] = t;
+            *wbase = t ? atomicAdd(S.count, static_cast<unsigned long long>(t)) - S.count_base : 0ull;
+        }
+        __syncthreads();
+        const int32_t total = wpre[waves_per_block];
+        const unsigned long long base = *wbase;
+        for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
+            int j = 0;
+            while (wpre[j + 1] <= i) ++j;
+            const uint32_t *pr = squeue + j * kQueueCap + 2 + 2 * (i - wpre[j]);
+            const uint32_t ent = pr[0];
+            const unsigned long long idx = base + unsigned(i);
+            if (idx < static_cast<unsigned long long>(S.cap)) {
+                S.out_off[idx] = offset_of(ent);
+                S.out_pid[idx] = int32_t(pr[1]);
+            }
+        }
+    } else {
+        // A batch: the block walks the hits its waves stored, spread over all
+        // its threads (one flat index over the waves' regions), once every
+        // wave is done.  The filter and queues are then free, so their LDS
+        // holds the match stage (one global atomic per block) and the
+        // batch's text starts for the walks' text lookups.
+        // Each wave leaves its hit count in its own (empty) queue; after the
+        // barrier the stage and the prefix sums of the counts go where the
+        // filter was.
+        if (lane == 0) q[0] = uint32_t(hcount);
+        __syncthreads();
+        static_assert((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 <= (1u << FLOG2),
+                      "the walk's stage must fit where the filter was");
+        MatchStage *st = reinterpret_cast<MatchStage *>(sfilt);
+        int32_t *wfirst = reinterpret_cast<int32_t *>(sfilt + (sizeof(MatchStage) + 15) / 16 * 16);   // [waves + 1]
+        if (threadIdx.x == 0) {
+            wfirst[0] = 0;
+            for (int j = 0; j < waves_per_block; ++j) wfirst[j + 1] = wfirst[j] + int32_t(squeue[j * kQueueCap]);
+            st->n = 0;
+        }
+        __syncthreads();
+        const int32_t total = wfirst[waves_per_block];
+        // The text starts (as offsets from the first text) are copied to LDS
+        // when they fit, beside the stage or where the prefix table was.
+        constexpr int kStageEnd = ((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 + 15) / 16 * 16;
+        constexpr int kLdsTexts = FLOG2 >= 17 ? ((1 << FLOG2) - kStageEnd) / 4 : 2 * PT_SLOTS;
+        static_assert(kLdsTexts >= 4096, "room for the text starts of a batch of 4096 texts");
+        uint32_t *lds_off = FLOG2 >= 17 ? reinterpret_cast<uint32_t *>(sfilt + kStageEnd) : sptab;
+        const uint32_t *loff = nullptr;
+        if (total > 0 && S.n_texts < kLdsTexts && S.n < (int64_t(1) << 32)) {
+            const int64_t base0 = S.text_off[0];
+            for (int i = int(threadIdx.x); i <= S.n_texts; i += int(blockDim.x)) lds_off[i] = uint32_t(S.text_off[i] - base0);
+            __syncthreads();
+            loff = lds_off;
+        }
+        for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
+            int j = 0;
+            while (wfirst[j + 1] <= i) ++j;          // wave (region) of flat index i
+            const uint4 rec = F.hits[(r0 + j) * F.hit_cap + (i - wfirst[j])];
+            const int64_t o = offset_of(rec.x);
+            int64_t tstart, end;
+            int32_t tid;
+            locate_text(S, loff, o, tstart, end, tid);
+            walk_rest<true>(A, S, o, end, rec.y, make_uint2(rec.z, rec.w),
+                            [&](int32_t s2) { emit_staged(A, S, st, o - tstart, tid, s2); },
+                            [&](int32_t pid) { emit_one(S, st, o - tstart, tid, pid); });
+        }
+        flush_stage(S, st);
+    }
 
     // The last block to finish hands the count to the host, once every
     // block's matches are stored: the barrier waits for this block's stores,
@@ -826,14 +1035,14 @@ __global__ __launch_bounds__(256) void probe_read_kernel(const uint8_t *buf, int
     if (lane_id() == 0 && acc == 0x9E3779B9u) *out = acc;   // practically never taken
 }
 
-using FilteredFn = void (*)(const DevAut, const ScanArgs, const FilterLaunch);
+using FilteredFn = void (*)(const KArgs);
 
-template <int K, bool BM, int FLOG2, int STRIDE, bool DUAL = false>
+template <int K, bool BM, int FLOG2, int STRIDE, bool DUAL = false, bool PAIR = false>
 FilteredFn pick_segs(int segs) {
     switch (segs) {
-        case 1: return filtered_kernel<K, BM, 1, FLOG2, STRIDE, DUAL>;
-        case 2: return filtered_kernel<K, BM, 2, FLOG2, STRIDE, DUAL>;
-        default: return filtered_kernel<K, BM, 4, FLOG2, STRIDE, DUAL>;
+        case 1: return filtered_kernel<K, BM, 1, FLOG2, STRIDE, DUAL, PAIR>;
+        case 2: return filtered_kernel<K, BM, 2, FLOG2, STRIDE, DUAL, PAIR>;
+        default: return filtered_kernel<K, BM, 4, FLOG2, STRIDE, DUAL, PAIR>;
     }
 }
 
@@ -844,6 +1053,10 @@ FilteredFn pick_filter(int kind, int segs) {
         case AC_FILTER_BITS20: return pick_segs<K, true, 17, STRIDE>(segs);
         case AC_FILTER_BYTES16: return pick_segs<K, false, 16, STRIDE>(segs);
         case AC_FILTER_DUAL19: return pick_segs<K, true, 17, STRIDE, true>(segs);
+        case AC_FILTER_PAIR20:
+            // stride 4 only (resolve_launch never pairs it with another stride)
+            if constexpr (STRIDE == 4) return pick_segs<K, true, 17, STRIDE, false, true>(segs);
+            else return nullptr;
         default: return pick_segs<K, true, 16, STRIDE>(segs);
     }
 }
@@ -879,7 +1092,7 @@ FilteredGeom filtered_geom(const ac_automaton *a, const uint8_t *text, int64_t n
     F.n_chunks = (F.V + CH - 1) / CH;
     F.c_lo = F.mis > 0 ? 1 : 0;
     F.c_hi = F.V >= 16 ? (F.V - 16) / CH : 0;
-    F.filter_kind = cfg.filter;
+    F.filter = a->dfilter[stride_set(cfg.stride) * kNumFilterKinds + cfg.filter - 1];
     const int waves = cfg.block / kWave;
     const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
     const int64_t want = (std::max<int64_t>(interior, 1) + waves - 1) / waves;
@@ -921,18 +1134,26 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         // 0.32 at stride 1; 20000 byte keywords (28000 windows) 0.31 dual at
         // stride 2, 0.44 one map at stride 1, 0.48 dual at stride 1, 0.56 one
         // map at stride 2.  Stride 4 is used only when asked for.
-        const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_DUAL19;
+        const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20;
         const bool auto_stride = cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4;
+        const bool small_text = len < (int64_t(16) << 20);
         if (auto_stride) {
-            if (P.sampled && P.n_windows2 <= 65536) cfg.stride = 2;
-            else cfg.stride = 1;
+            if (auto_filter && !small_text && P.pair4 && P.n_quads4 <= kPairMaxKeys) {
+                cfg.stride = 4;
+                cfg.filter = AC_FILTER_PAIR20;
+            } else if (P.sampled && P.n_windows2 <= 65536) {
+                cfg.stride = 2;
+            } else {
+                cfg.stride = 1;
+            }
         }
         if (cfg.stride == 4 && !P.sampled4) cfg.stride = P.sampled ? 2 : 1;
         if (cfg.stride == 2 && !P.sampled) cfg.stride = 1;
-        if (auto_filter) {
+        // the 4-byte-window map exists at stride 4 only
+        if (cfg.filter == AC_FILTER_PAIR20 && (cfg.stride != 4 || !P.pair4)) cfg.filter = AC_FILTER_AUTO;
+        if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20) {
             // keys in the filter: prefixes (stride 1) or windows (strides 2, 4)
             const int64_t keys = cfg.stride == 4 ? P.n_windows4 : cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;
-            const bool small_text = len < (int64_t(16) << 20);
             if (small_text) cfg.filter = keys > 1500 ? AC_FILTER_BITS19 : AC_FILTER_BYTES16;
             else if (keys <= 1500) cfg.filter = AC_FILTER_BYTES17;
             else if (keys <= 8192) cfg.filter = AC_FILTER_BITS20;
@@ -943,20 +1164,21 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         if (filtered_lds(g) > a->lds_per_block) {
             // the 128 KiB maps need a 160 KiB LDS; fall back to the 64 KiB ones
             if (cfg.filter == AC_FILTER_BYTES17) cfg.filter = AC_FILTER_BYTES16;
-            if (cfg.filter == AC_FILTER_BITS20 || cfg.filter == AC_FILTER_DUAL19) cfg.filter = AC_FILTER_BITS19;
+            if (cfg.filter == AC_FILTER_BITS20 || cfg.filter == AC_FILTER_DUAL19 || cfg.filter == AC_FILTER_PAIR20)
+                cfg.filter = AC_FILTER_BITS19;
             g = filter_geom(cfg.filter);
         }
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
         // Texts under 32 MiB take one segment per wave step, which spreads
         // them over more waves (measured on MI355X: a 1 MiB scan in 11 us
-        // instead of 19 with four segments).  Above that, the single bit map
-        // at stride 1 takes two segments (four spill and ran 8% slower on
-        // 50000 keywords); the others take four, the dual map too (its
-        // four-segment kernels spill a little but ran 1-2% faster than two
-        // on 20000 and 50000 keywords).
+        // instead of 19 with four segments).  Above that, the dual map takes
+        // four segments and the others two (1 GiB on MI355X: 1000 keywords,
+        // 4-byte-window map at stride 4, 0.213 ms at two and 0.219 at four;
+        // 20000 keywords, dual map at stride 2, 0.269 ms at four and 0.283
+        // at two).
         if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) {
             if (len < (int64_t(32) << 20)) cfg.segs = 1;
-            else cfg.segs = (g.bitmap && !g.dual && cfg.stride == 1) ? 2 : 4;
+            else cfg.segs = g.dual ? 4 : 2;
         }
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
@@ -997,6 +1219,13 @@ int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, cons
     return filtered_geom(a, text, n, cfg).waves;
 }
 
+int64_t widest_scan_regions(int cu_count, int64_t lds_per_cu) {
+    // a filtered launch has at most (LDS per CU / the smallest filter's LDS)
+    // blocks per CU, each of at most kMaxWaves waves
+    return int64_t(cu_count) * std::max<int64_t>(1, lds_per_cu / filtered_lds(filter_geom(AC_FILTER_BITS19))) *
+           kMaxWaves;
+}
+
 int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, const HitScratch &hs,
                 hipStream_t stream, std::string &err, const KernelTiming *timing, int64_t *blocks) {
     if (blocks) *blocks = 0;
@@ -1008,19 +1237,22 @@ int launch_scan(const ac_automaton *a, const ScanArgs &S, const ac_launch &cfg, 
     if (cfg.policy == AC_POLICY_FILTERED) {
         FilteredGeom G = filtered_geom(a, S.text, S.n, cfg);
         FilterLaunch &F = G.F;
-        if (!hs.hits || hs.regions < G.waves || hs.cap <= 0) {
+        if (!hs.hits || hs.regions < G.waves || hs.cap < kDrain) {
             err = "scan scratch too small for the launch";
             return AC_EINVAL;
         }
         F.hits = hs.hits;
         F.hit_cap = hs.cap;
         const int64_t interior = std::max<int64_t>(0, F.c_hi - F.c_lo);
-        // queue entries hold (chunk step << 12 | position): steps must fit 20 bits
-        if (interior / G.waves >= (int64_t(1) << 20)) { err = "text too large for one launch"; return AC_EINVAL; }
+        // queue entries hold (slot << 12 | position): a block's slots must fit 20 bits
+        if (interior / G.grid + 2 * (cfg.block / kWave) >= (int64_t(1) << 20)) {
+            err = "text too large for one launch";
+            return AC_EINVAL;
+        }
         FilteredFn fn = pick_filtered(P.K, cfg.filter, cfg.segs, cfg.stride);
-        DevAut A = a->dev;
-        ScanArgs SA = S;
-        void *fargs[] = {&A, &SA, &F};
+        if (!fn) { err = "no kernel for this filter and stride"; return AC_EINVAL; }
+        KArgs KA{a->dev, S, F};
+        void *fargs[] = {&KA};
         e = launch_timed(reinterpret_cast<const void *>(fn), dim3(unsigned(G.grid)), dim3(unsigned(cfg.block)), fargs, 0,
                          stream, T.scan0, T.scan1);
         if (blocks && e == hipSuccess) *blocks = G.grid;

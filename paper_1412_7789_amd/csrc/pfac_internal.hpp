@@ -30,23 +30,29 @@ struct FilterGeom {
     int shift;       // product >> shift gives the byte (byte map) or word (bit map) index
     int64_t bytes;   // LDS bytes
     bool dual;       // two bit maps with independent hashes, both must be set
+    bool pair;       // two bits per key in one word (4-byte keys), both must be set
 };
 
 inline FilterGeom filter_geom(int kind) {
     switch (kind) {
-        case AC_FILTER_BYTES17: return {kind, false, 17, 32 - 17, 1ll << 17, false};
-        case AC_FILTER_BITS20:  return {kind, true, 20, 32 - 15, 1ll << 17, false};
-        case AC_FILTER_BYTES16: return {kind, false, 16, 32 - 16, 1ll << 16, false};
-        case AC_FILTER_BITS19:  return {kind, true, 19, 32 - 14, 1ll << 16, false};
-        case AC_FILTER_DUAL19:  return {kind, true, 19, 32 - 14, 1ll << 17, true};
-        default: return {0, false, 0, 0, 0, false};
+        case AC_FILTER_BYTES17: return {kind, false, 17, 32 - 17, 1ll << 17, false, false};
+        case AC_FILTER_BITS20:  return {kind, true, 20, 32 - 15, 1ll << 17, false, false};
+        case AC_FILTER_BYTES16: return {kind, false, 16, 32 - 16, 1ll << 16, false, false};
+        case AC_FILTER_BITS19:  return {kind, true, 19, 32 - 14, 1ll << 16, false, false};
+        case AC_FILTER_DUAL19:  return {kind, true, 19, 32 - 14, 1ll << 17, true, false};
+        case AC_FILTER_PAIR20:  return {kind, true, 20, 32 - 15, 1ll << 17, false, true};
+        default: return {0, false, 0, 0, 0, false, false};
     }
 }
-constexpr int kNumFilterKinds = 5;
+constexpr int kNumFilterKinds = 6;
 constexpr uint32_t kFilterMul2 = 0x7FEB35u;       // hash of the second map of AC_FILTER_DUAL19
-// Filter sets: [0, 4) test every offset against the keywords' K-byte
-// prefixes; [4, 8) test odd offsets against the 3-byte windows at keyword
-// positions 0 and 1 (built when K = 3 and every keyword has >= 4 bytes).
+// Filter sets, kNumFilterKinds maps each: stride 1 tests every offset against
+// the keywords' K-byte prefixes; stride 2 tests the windows starting at every
+// second offset against the 3-byte windows at keyword positions 1 and 2
+// (built when K = 3 and every keyword has >= 5 bytes); stride 4 every fourth
+// one against positions 1 .. 4 (keywords of >= 7 bytes), and its
+// AC_FILTER_PAIR20 map holds the 4-byte windows there (keywords of >= 8
+// bytes).  A set's AC_FILTER_PAIR20 slot is empty at strides 1 and 2.
 constexpr int kNumFilters = 3 * kNumFilterKinds;   // strides 1, 2 and 4
 // Filter set of a sampling stride: 0 (stride 1), 1 (stride 2), 2 (stride 4).
 constexpr int stride_set(int stride) { return stride == 4 ? 2 : stride - 1; }
@@ -69,11 +75,13 @@ struct Plan {
     std::vector<int32_t> node;     // [2 * (S - S_dense)]
     uint32_t hash_mul = kDefaultHashMul;
     int32_t n_prefixes = 0;
-    int32_t n_windows2 = 0;        // distinct 3-byte windows at keyword positions 0 and 1
+    int32_t n_windows2 = 0;        // distinct 3-byte windows at keyword positions 1 and 2
     bool sampled = false;          // the stride-2 filters exist
-    int32_t n_windows4 = 0;        // distinct 3-byte windows at keyword positions 0 .. 3
+    int32_t n_windows4 = 0;        // distinct 3-byte windows at keyword positions 1 .. 4
     bool sampled4 = false;         // the stride-4 filters exist
-    std::vector<uint8_t> filter[kNumFilters];   // indexed by stride_set(stride) * 4 + kind - 1
+    int32_t n_quads4 = 0;          // distinct 4-byte windows at keyword positions 1 .. 4
+    bool pair4 = false;            // the stride-4 AC_FILTER_PAIR20 map exists
+    std::vector<uint8_t> filter[kNumFilters];   // indexed by stride_set(stride) * kNumFilterKinds + kind - 1
     int32_t ptab_bits = 0;
     std::vector<uint32_t> ptab;    // [2 << ptab_bits]: buckets of 4 {key, value} slots
     std::vector<int32_t> tail;     // [S]: leaf of a forced path, or -1
@@ -83,21 +91,21 @@ struct Plan {
     double build_ms = 0.0;
 };
 
-// Kernel-side view of a device automaton (passed by value).
+// Kernel-side view of a device automaton (passed by value).  It holds only
+// what the walks read: every field is a kernel argument kept in scalar
+// registers, so the filter maps (one of which a launch stages in LDS) travel
+// in the launch's own arguments instead.
 struct DevAut {
     const uint8_t *cls;
-    const uint8_t *filter[kNumFilters];
     const int32_t *dense;
     const int32_t *node;
     const uint8_t *label;
     const int32_t *out_off;
     const int32_t *out_pid;
     const uint32_t *ptab;          // exact prefix table (global copy)
-    const int32_t *tail;
     const int4 *tailinfo;
     const uint8_t *kw_bytes;
-    const int32_t *kw_off;
-    int32_t C, S, S_dense, K, max_len;
+    int32_t C, S_dense, K;
     int32_t ptab_bits;
     uint32_t hash_mul;
 };
@@ -138,6 +146,7 @@ struct ac_automaton {
     void *dmem = nullptr;          // one device allocation for every table
     int64_t dbytes = 0;
     pfac::DevAut dev{};
+    const uint8_t *dfilter[pfac::kNumFilters] = {};   // device filter maps, by stride_set * kinds + kind - 1
     int cu_count = 0;
     int64_t lds_per_block = 0;
     int64_t lds_per_cu = 0;
@@ -153,7 +162,8 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
 uint32_t prefix_hash(uint32_t x, uint32_t mul);
 // The two candidate buckets (of 4 slots) of prefix x in a table of 2^bits slots.
 void prefix_buckets(uint32_t x, uint32_t mul, int bits, uint32_t &b1, uint32_t &b2);
-// Per-stream scratch of the filtered policy: one hit region per streaming wave.
+// Per-stream scratch of the filtered policy: one hit region per streaming
+// wave of the widest launch.
 struct HitScratch {
     uint4 *hits = nullptr;         // [regions * cap]
     int64_t regions = 0;
@@ -163,6 +173,8 @@ constexpr int32_t kHitCap = 1024;
 
 // kernels.hip
 int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
+// Hit regions of the widest filtered launch on a device.
+int64_t widest_scan_regions(int cu_count, int64_t lds_per_cu);
 // Start/stop events of the scan kernel (the filtered policy's streaming
 // kernel or the direct kernel), taken from its own dispatch packet so that
 // they time the kernel alone; null = untimed.
@@ -181,8 +193,11 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
 // Sets the calling thread's ac_last_error() message; returns `code`.
 int report_error(int code, const std::string &msg);
 
-// Creates the (current device, stream) scratch now, with room for `regions`
-// hit regions, so that later scans on the stream allocate nothing.
-int reserve_stream_scratch(hipStream_t stream, int64_t regions);
+// Creates the (current device, stream) scratch now, so that later scans on
+// the stream allocate nothing.
+int reserve_stream_scratch(hipStream_t stream);
+// Frees the (current device, stream) scratch; the stream must be idle and is
+// about to be destroyed.
+void release_stream_scratch(hipStream_t stream);
 int launch_probe_read(const uint8_t *buf, int64_t n, uint32_t *out, hipStream_t stream, std::string &err);
 }  // namespace pfac

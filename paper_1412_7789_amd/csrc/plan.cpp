@@ -261,45 +261,83 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
     prefixes.erase(std::unique(prefixes.begin(), prefixes.end()), prefixes.end());
     P.n_prefixes = int32_t(prefixes.size());
     // windows for the sampled filters: bytes [j, j + 3) of each keyword for
-    // j < 2 (stride 2, keywords of 4 bytes or more) and j < 4 (stride 4, 6
-    // bytes or more)
+    // j = 1, 2 (stride 2, keywords of 5 bytes or more) and j = 1 .. 4 (stride
+    // 4, 7 bytes or more)
     auto windows_of = [&](int count) {
         std::vector<uint32_t> w;
         w.reserve(size_t(n) * size_t(count));
         for (int32_t p = 0; p < n; ++p) {
             const uint8_t *k = kw(p);
-            for (int j = 0; j < count; ++j)
+            for (int j = 1; j <= count; ++j)
                 w.push_back(uint32_t(k[j]) | uint32_t(k[j + 1]) << 8 | uint32_t(k[j + 2]) << 16);
         }
         std::sort(w.begin(), w.end());
         w.erase(std::unique(w.begin(), w.end()), w.end());
         return w;
     };
-    P.sampled = P.K == 3 && P.min_len >= 4;
-    P.sampled4 = P.K == 3 && P.min_len >= 6;
+    P.sampled = P.K == 3 && P.min_len >= 5;
+    P.sampled4 = P.K == 3 && P.min_len >= 7;
     const std::vector<uint32_t> windows = P.sampled ? windows_of(2) : std::vector<uint32_t>();
     const std::vector<uint32_t> windows4 = P.sampled4 ? windows_of(4) : std::vector<uint32_t>();
     P.n_windows2 = int32_t(windows.size());
     P.n_windows4 = int32_t(windows4.size());
+    // 4-byte windows at positions 1 .. 4 (keywords of 8 bytes or more)
+    P.pair4 = P.K == 3 && P.min_len >= 8;
+    std::vector<uint32_t> quads4;
+    if (P.pair4) {
+        quads4.reserve(size_t(n) * 4);
+        for (int32_t p = 0; p < n; ++p) {
+            const uint8_t *k = kw(p);
+            for (int j = 1; j <= 4; ++j)
+                quads4.push_back(uint32_t(k[j]) | uint32_t(k[j + 1]) << 8 | uint32_t(k[j + 2]) << 16 |
+                                 uint32_t(k[j + 3]) << 24);
+        }
+        std::sort(quads4.begin(), quads4.end());
+        quads4.erase(std::unique(quads4.begin(), quads4.end()), quads4.end());
+    }
+    P.n_quads4 = int32_t(quads4.size());
+    // A key x with hash h = x * mul (mod 2^32) owns bit h mod 32 of word (or
+    // byte) h >> shift.  The sampled kernels hash x * mul + c with 0 <= c <
+    // 32, which may carry into the index: those maps also set the key's bit
+    // at index (h + 31) >> shift, so every c finds it.
     for (int set = 0; set < 3; ++set) {
         const std::vector<uint32_t> &keys = set == 0 ? prefixes : set == 1 ? windows : windows4;
+        const uint32_t carry = set == 0 ? 0u : 31u;
         for (int kind = 1; kind <= kNumFilterKinds; ++kind) {
             FilterGeom g = filter_geom(kind);
             std::vector<uint8_t> &f = P.filter[set * kNumFilterKinds + kind - 1];
             if ((set == 1 && !P.sampled) || (set == 2 && !P.sampled4)) { f.clear(); continue; }
+            if (g.pair) {
+                // 4-byte window x: bits h mod 32 and (x >> 24) mod 32 of word h >> shift,
+                // h the hash of its first three bytes (the kernel adds nothing to h)
+                if (set != 2 || !P.pair4) { f.clear(); continue; }
+                f.assign(size_t(g.bytes), 0);
+                for (uint32_t x : quads4) {
+                    const uint32_t h = prefix_hash(x & 0xFFFFFFu, mul);
+                    const size_t w = size_t(h >> g.shift) * 4;
+                    for (uint32_t bit : {h & 31u, (x >> 24) & 31u}) f[w + bit / 8] |= uint8_t(1u << (bit % 8));
+                }
+                continue;
+            }
             f.assign(size_t(g.bytes), 0);
+            // one bit map of `words` 32-bit words starting at byte `at`
+            auto set_bit = [&](size_t at, uint32_t h, int shift) {
+                const uint32_t bit = h & 31u;
+                for (uint32_t hh : {h, h + carry}) {
+                    const uint32_t w = hh >> shift;
+                    f[at + size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
+                }
+            };
             for (uint32_t x : keys) {
-                uint32_t h = prefix_hash(x, mul);
-                if (g.bitmap) {
-                    uint32_t w = h >> g.shift, bit = h & 31u;
-                    f[size_t(w) * 4 + bit / 8] |= uint8_t(1u << (bit % 8));
-                    if (g.dual) {   // map B: the second half, its own hash
-                        const uint32_t h2 = prefix_hash(x, kFilterMul2);
-                        const uint32_t w2 = h2 >> g.shift, bit2 = h2 & 31u;
-                        f[size_t(g.bytes / 2) + size_t(w2) * 4 + bit2 / 8] |= uint8_t(1u << (bit2 % 8));
-                    }
+                const uint32_t h = prefix_hash(x, mul);
+                if (g.dual) {   // map A, then map B with its own hash: both halves of the bytes
+                    set_bit(0, h, g.shift);
+                    set_bit(size_t(g.bytes / 2), prefix_hash(x, kFilterMul2), g.shift);
+                } else if (g.bitmap) {
+                    set_bit(0, h, g.shift);
                 } else {
                     f[size_t(h >> g.shift)] = 1;
+                    f[size_t((h + carry) >> g.shift)] = 1;
                 }
             }
         }

@@ -171,7 +171,11 @@ void release_slot(Slot &s) {
                     static_cast<void *>(s.h_off), static_cast<void *>(s.h_pid), static_cast<void *>(s.h_count)})
         if (p) (void)hipHostFree(p);
     if (s.ev) (void)hipEventDestroy(s.ev);
-    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.stream) {
+        (void)hipStreamSynchronize(s.stream);
+        pfac::release_stream_scratch(s.stream);
+        (void)hipStreamDestroy(s.stream);
+    }
     s = Slot();
 }
 
@@ -424,9 +428,6 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
     s->o = o;
     hipError_t e = hipGetDevice(&s->device);
     int rc = e == hipSuccess ? AC_OK : report_error(AC_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
-    int cus = 1;
-    if (!rc && (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess)
-        rc = report_error(AC_EHIP, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(e));
     s->slots.resize(size_t(o.n_streams));
     for (auto &sl : s->slots) {
         if (rc) break;
@@ -436,8 +437,8 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
             break;
         }
         if ((rc = dev_alloc(&sl.d_count, 1)) || (rc = host_alloc(&sl.h_count, 1))) break;
-        // the scan's hit regions for the widest launch (16 waves per CU)
-        if ((rc = pfac::reserve_stream_scratch(sl.stream, int64_t(cus) * 16))) break;
+        // the scan's scratch: hit regions for the widest launch
+        if ((rc = pfac::reserve_stream_scratch(sl.stream))) break;
         // sized for a full batch, so that serving never reallocates (a single
         // request longer than max_batch_bytes still grows its stream's buffers)
         const int64_t texts = std::min<int64_t>(o.max_batch_texts, 1 << 16);

@@ -226,45 +226,95 @@ def test_prefix_table_and_tails(name, kws):
 
 def test_filters_have_no_false_negatives():
     """Every key of each filter set is present in every map of that set:
-    K-byte prefixes (stride 1), windows [0,3) and [1,4) (stride 2) and
-    windows [0,3) .. [3,6) (stride 4)."""
+    K-byte prefixes (stride 1), windows [1,4) and [2,5) (stride 2) and
+    windows [1,4) .. [4,7) (stride 4).  A key with hash h owns bit h mod 32
+    of word h >> shift; the sampled maps set it at index (h + 31) >> shift
+    too, since their kernels add up to 31 to the hash before indexing."""
     kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
     T = Tables(kws)
     K = T.info["prefix_len"]
     assert K == 3
     geoms = {1: (False, 17), 2: (True, 17), 3: (False, 16), 4: (True, 16)}
     key_sets = {0: {k[:K] for k in kws},
-                1: {k[j:j + 3] for k in kws for j in range(2)},
-                2: {k[j:j + 3] for k in kws for j in range(4)}}
+                1: {k[j:j + 3] for k in kws for j in (1, 2)},
+                2: {k[j:j + 3] for k in kws for j in (1, 2, 3, 4)}}
     assert T.info["n_windows2"] == len(key_sets[1])
     assert T.info["n_windows4"] == len(key_sets[2])
+    M32 = 0xFFFFFFFF
     for set_, keys in key_sets.items():
+        carries = (0,) if set_ == 0 else (0, 31)
         for kind, (bitmap, flog2) in geoms.items():
-            f = T.plan.export(L.AC_TABLE_FILTER_BASE + 5 * set_ + kind, np.uint8)
+            f = T.plan.export(L.AC_TABLE_FILTER_BASE + 6 * set_ + kind, np.uint8)
             assert len(f) == 1 << flog2
             for key in keys:
                 h = T.plan.hash(int.from_bytes(key, "little"))
-                if bitmap:
-                    w = f.view(np.uint32)[h >> (32 - (flog2 - 2))]
-                    assert (int(w) >> (h & 31)) & 1
-                else:
-                    assert f[h >> (32 - flog2)] == 1
+                for c in carries:
+                    hc = (h + c) & M32
+                    if bitmap:
+                        w = f.view(np.uint32)[hc >> (32 - (flog2 - 2))]
+                        assert (int(w) >> (h & 31)) & 1
+                    else:
+                        assert f[hc >> (32 - flog2)] == 1
         # dual map: 2^19 bits hashed as `hash`, then 2^19 bits hashed as `hash2`
-        f = T.plan.export(L.AC_TABLE_FILTER_BASE + 5 * set_ + L.AC_FILTER_DUAL19, np.uint8).view(np.uint32)
+        f = T.plan.export(L.AC_TABLE_FILTER_BASE + 6 * set_ + L.AC_FILTER_DUAL19, np.uint8).view(np.uint32)
         assert len(f) == 2 << 14
         for key in keys:
             x = int.from_bytes(key, "little")
             h1, h2 = T.plan.hash(x), T.plan.hash2(x)
             assert h1 != h2 or x == 0
-            assert (int(f[h1 >> 18]) >> (h1 & 31)) & 1
-            assert (int(f[(1 << 14) + (h2 >> 18)]) >> (h2 & 31)) & 1
+            for c in carries:
+                assert (int(f[((h1 + c) & M32) >> 18]) >> (h1 & 31)) & 1
+                assert (int(f[(1 << 14) + (((h2 + c) & M32) >> 18)]) >> (h2 & 31)) & 1
+
+
+def test_rotated_bit_test_finds_every_key():
+    """The sampled kernels test key x for destination bit b by hashing p =
+    x * mul + c with c = -b mod 32, reading word p >> shift and rotating it
+    right by p mod 32: the key's bit must land on bit b, for every b they
+    use (0 .. 14 at stride 2, 0, 4, 8, 12 at stride 4)."""
+    kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
+    T = Tables(kws)
+    words = T.plan.export(L.AC_TABLE_FILTER_BASE + 6 * 1 + L.AC_FILTER_BITS20, np.uint8).view(np.uint32)
+    M32 = 0xFFFFFFFF
+    rot = lambda v, r: ((v >> r) | (v << (32 - r))) & M32 if r else v
+    for key in sorted({k[j:j + 3] for k in kws for j in (1, 2)})[:500]:
+        h = T.plan.hash(int.from_bytes(key, "little"))
+        for b in range(0, 16, 2):
+            p = (h + ((32 - b) & 31)) & M32
+            assert (rot(int(words[p >> 17]), p & 31) >> b) & 1
+
+
+def test_pair_map_holds_both_bits_of_every_4_byte_window():
+    """AC_FILTER_PAIR20 (stride 4): every 4-byte window x at keyword
+    positions 1 .. 4 owns bits h mod 32 and (x >> 24) mod 32 of word h >> 17,
+    h the hash of its first three bytes; the map exists only at stride 4."""
+    kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
+    T = Tables(kws)
+    quads = {k[j:j + 4] for k in kws for j in (1, 2, 3, 4)}
+    assert T.info["n_quads4"] == len(quads)
+    words = T.plan.export(L.AC_TABLE_FILTER_BASE + 12 + L.AC_FILTER_PAIR20, np.uint8).view(np.uint32)
+    assert len(words) == 1 << 15
+    for q in quads:
+        x = int.from_bytes(q, "little")
+        h = T.plan.hash(x & 0xFFFFFF)
+        w = int(words[h >> 17])
+        assert (w >> (h & 31)) & 1 and (w >> ((x >> 24) & 31)) & 1
+    # bits set: at most two per window
+    assert sum(bin(int(v)).count("1") for v in words) <= 2 * len(quads)
+    for set_ in (0, 1):
+        assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 6 * set_ + L.AC_FILTER_PAIR20, np.uint8)) == 0
+    # keywords shorter than 8 bytes: no 4-byte-window map
+    T7 = Tables([b"abcdefg", b"bcdefghij"])
+    assert T7.info["n_quads4"] == 0 and T7.info["n_windows4"] > 0
 
 
 def test_sampled_filters_need_long_enough_keywords():
-    T = Tables([b"abcde", b"bcdefg"])          # shortest 5: stride 2 only
+    T = Tables([b"abcdef", b"bcdefg"])         # shortest 6: stride 2 only
     assert T.info["n_windows2"] > 0 and T.info["n_windows4"] == 0
-    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 12, np.uint8)) == 0
-    T = Tables([b"abc", b"abcdef"])            # shortest 3: neither
+    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 12 + L.AC_FILTER_BITS19, np.uint8)) == 0
+    T = Tables([b"abcdefg", b"bcdefgh"])       # shortest 7: both
+    assert T.info["n_windows2"] > 0 and T.info["n_windows4"] > 0
+    T = Tables([b"abcd", b"abcdef"])           # shortest 4: neither
     assert T.info["n_windows2"] == 0 and T.info["n_windows4"] == 0
 
 

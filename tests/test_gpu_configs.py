@@ -1,11 +1,12 @@
 """GPU parity on the benchmark workloads, at their real sizes.
 
-* sweep (1000 printable keywords): every size of the x16 sweep up to 64 MiB
-  compared in full with the oracle; 1 GiB (the benchmark's launch
-  configuration) checked on exact oracle windows plus soundness of every match
-  and completeness of every surviving plant.
+* sweep (1000 printable keywords): every size of the x16 sweep up to 1 GiB
+  compared in full with the oracle (1 GiB in the benchmark's launch
+  configuration, the oracle run over slices on host threads), plus soundness
+  of every match, completeness of every surviving plant and sampled
+  per-keyword counts at 1 GiB.
 * large automaton (20000 byte keywords, ~734k states, compact layout): 64 MiB
-  in full, 1 GiB by windows.
+  and 1 GiB in full.
 * batched (2000 keywords, 4096 log-normal texts): every text against the
   oracle, and the batch against per-text calls.
 """
@@ -16,7 +17,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle
-from tests.helpers import as_pairs, assert_same
+from tests.helpers import as_pairs, assert_same, oracle_sliced
 from workloads import GIB, MIB, config_batched, config_large_automaton, config_sweep
 
 torch = pytest.importorskip("torch")
@@ -54,21 +55,6 @@ def check_sound(keywords, text, off, pid):
         assert (o >= 0).all() and (o + len(k) <= len(text)).all()
         win = text[o[:, None] + np.arange(len(k))[None, :]]
         assert (win == k[None, :]).all(), f"unsound match for keyword {p}"
-
-
-def check_windows(keywords, text, off, pid, n_windows=6, width=4 * MIB, seed=0):
-    """Exact comparison on oracle windows: the GPU matches lying wholly inside
-    a window equal the oracle's result on that window."""
-    rng = np.random.default_rng(seed)
-    lens = np.array([len(k) for k in keywords], dtype=np.int64)
-    o_or = Oracle(keywords)
-    starts = [0, len(text) - width] + list(rng.integers(0, len(text) - width, size=n_windows - 2))
-    for w0 in starts:
-        w1 = w0 + width
-        eo, ep = o_or.match(text[w0:w1])
-        sel = (off >= w0) & (off + lens[pid] <= w1)
-        assert_same((off[sel] - w0, pid[sel]), (eo, ep), f"window {w0}")
-    o_or.close()
 
 
 def count_overlapping(text_bytes, k):
@@ -110,9 +96,18 @@ def test_sweep_policies_agree():
     a = pf.Automaton(w.keywords)
     exp = Oracle(w.keywords).match(w.text)
     for cfg in [dict(policy=1, filter=f, segs=s, block=b, stride=st) for f in (1, 2, 3, 4, 5) for s in (1, 2, 4)
-                for b in (256, 1024) for st in (1, 2, 4)] + [dict(policy=2)]:
+                for b in (256, 1024) for st in (1, 2, 4)] + \
+               [dict(policy=1, filter=6, segs=s, block=b, stride=4) for s in (1, 2, 4) for b in (256, 512, 1024)] + \
+               [dict(policy=2)]:
         say("sweep policy", cfg)
         assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
+
+
+def full_oracle(keywords, text):
+    o = Oracle(keywords)
+    (res,) = oracle_sliced(o, max(len(k) for k in keywords), [text])
+    o.close()
+    return res
 
 
 def test_sweep_1gib_launch():
@@ -122,9 +117,10 @@ def test_sweep_1gib_launch():
     off, pid = run_gpu(a, w.text)
     off, pid = as_pairs(off, pid)
     assert len(off) > 250_000
+    say("sweep 1 GiB: oracle")
+    assert_same((off, pid), full_oracle(w.keywords, w.text), "sweep 1 GiB")
     check_sound(w.keywords, w.text, off, pid)
     check_plants(w.keywords, w.text, off, pid, w.plants)
-    check_windows(w.keywords, w.text, off, pid)
     check_sampled_counts(w.keywords, w.text, pid)
 
 
@@ -137,7 +133,8 @@ def test_large_automaton_64mib_full():
     exp = Oracle(w.keywords).match(w.text)
     assert_same(run_gpu(a, w.text), exp, "large 64 MiB")
     for cfg in [dict(policy=1, filter=1, stride=1), dict(policy=1, filter=4, segs=1, stride=2),
-                dict(policy=1, filter=2, stride=2), dict(policy=1, filter=5, stride=1), dict(policy=2)]:
+                dict(policy=1, filter=2, stride=2), dict(policy=1, filter=5, stride=1),
+                dict(policy=1, filter=6, stride=4), dict(policy=2)]:
         say("large policy", cfg)
         assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
 
@@ -145,13 +142,13 @@ def test_large_automaton_64mib_full():
 def test_large_automaton_1gib_launch():
     w = config_large_automaton(GIB)
     a = pf.Automaton(w.keywords)
-    say("large 1 GiB")
+    say("large 1 GiB", a.default_launch(GIB))
     off, pid = run_gpu(a, w.text)
     off, pid = as_pairs(off, pid)
+    say("large 1 GiB: oracle")
+    assert_same((off, pid), full_oracle(w.keywords, w.text), "large 1 GiB")
     check_sound(w.keywords, w.text, off, pid)
     check_plants(w.keywords, w.text, off, pid, w.plants)
-    check_windows(w.keywords, w.text, off, pid, n_windows=4)
-    check_sampled_counts(w.keywords, w.text, pid)
 
 
 def test_pid_permutation_and_keyword_subsets():

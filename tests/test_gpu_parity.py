@@ -56,6 +56,7 @@ POLICIES = [
     ("stride4-falls-back", dict(policy=1, filter=2, segs=4, stride=4)),
     ("dual19-s4", dict(policy=1, filter=5, segs=4)),
     ("dual19-stride1-s2-b512", dict(policy=1, filter=5, segs=2, stride=1, block=512)),
+    ("pair20-falls-back", dict(policy=1, filter=6, segs=4, stride=4)),
     ("direct-lds", dict(policy=2, table_in_lds=1)),
     ("direct-global", dict(policy=2, table_in_lds=2)),
 ]
@@ -168,18 +169,86 @@ def test_errors_are_reported():
         a.count(t, launch=pf.launch_config(block=100))
 
 
-@pytest.mark.parametrize("stride", [1, 2, 4])
-def test_hit_region_overflow(stride):
+@pytest.mark.parametrize("stride,filt", [(1, 0), (2, 0), (4, 0), (4, 6)])
+def test_hit_region_overflow(stride, filt):
     """A periodic text where a third of all offsets match fills every wave's
-    hit region many times over, so the streaming kernel's post-pass walks the
-    chunks whose hits were dropped (and the final walk skips their stored
-    records)."""
-    kws = [b"abcab", b"cabca", b"zzzz"] if stride < 4 else [b"abcabc", b"cabcab", b"zzzzzz"]
+    hit region at once, so every wave leaves the streaming loop for the slow
+    mode that walks each hit as the prefix table confirms it."""
+    kws = [b"abcab", b"cabca", b"zzzz"] if stride < 4 else [b"abcabcab", b"cabcabca", b"zzzzzzzz"]
     text = np.frombuffer(b"abc" * (16 << 20 // 3), dtype=np.uint8)
     text = np.ascontiguousarray(text[: 16 << 20])
-    say("overflow", stride, len(text))
-    cfg = pf.launch_config(policy=1, stride=stride, segs=4)
+    say("overflow", stride, filt, len(text))
+    cfg = pf.launch_config(policy=1, stride=stride, segs=4, filter=filt)
     assert_same(gpu_match(kws, text, launch=cfg), oracle_match(kws, text), f"overflow stride {stride}")
+
+
+@pytest.mark.parametrize("cfg", [None, dict(policy=1, stride=2, filter=2, segs=4),
+                                 dict(policy=1, stride=4, filter=6, segs=2), dict(policy=1, stride=1, segs=1)])
+def test_dense_stretch_sends_some_waves_to_slow_mode(cfg):
+    """32 MiB of the 1000-keyword workload with 2 MiB of one repeated byte
+    in the middle and two keywords made of that byte: the waves that draw the
+    dense chunks overflow their hit regions and finish in the slow mode, the
+    others stay in the streaming loop; the whole match set against the
+    oracle, single text and as a batch of 7 uneven texts."""
+    from workloads import config_sweep
+    w = config_sweep(32 << 20)
+    text = w.text.copy()
+    text[15 << 20:17 << 20] = ord("a")
+    kws = list(w.keywords) + [b"a" * 8, b"a" * 12]
+    a = pf.Automaton(kws)
+    exp = oracle_match(kws, text)
+    launch = pf.launch_config(**cfg) if cfg else None
+    say("dense stretch", cfg, a.default_launch(len(text)))
+    assert_same(gpu_match(kws, text, launch=launch, automaton=a), exp, f"dense stretch {cfg}")
+    cuts = np.array([0, 1 << 20, 15 << 20, (15 << 20) + 12345, 16 << 20, 17 << 20, 30 << 20, 32 << 20], dtype=np.int64)
+    tid, off, pid, per = (x.cpu().numpy() for x in a.match_batch(torch.from_numpy(text).cuda(),
+                                                                  torch.from_numpy(cuts).cuda(), launch=launch))
+    for t in range(len(cuts) - 1):
+        seg = text[cuts[t]:cuts[t + 1]]
+        sel = tid == t
+        assert_same((off[sel], pid[sel]), oracle_match(kws, seg), f"batch text {t} {cfg}")
+
+
+def test_graph_stays_valid_after_larger_calls_on_its_stream():
+    """A scan captured in a HIP graph keeps its stream's scratch: larger
+    synchronous and asynchronous calls on the same stream in between (the
+    scratch is sized for the widest launch when the stream is first used)
+    leave every replay equal to the oracle."""
+    from workloads import config_sweep
+    w = config_sweep(1 << 20)
+    a = pf.Automaton(w.keywords)
+    exp = oracle_match(w.keywords, w.text)
+    n = len(exp[0])
+    t = torch.from_numpy(w.text).cuda()
+    off = torch.empty(n + 8, dtype=torch.int64, device="cuda")
+    pid = torch.empty(n + 8, dtype=torch.int32, device="cuda")
+    d_count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    big = config_sweep(64 << 20)
+    tb = torch.from_numpy(big.text).cuda()
+    nb = len(oracle_match(big.keywords, big.text)[0])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.match_async(t, off, pid, d_count, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.match_async(t, off, pid, d_count, stream=s)
+    for r in range(3):
+        with torch.cuda.stream(s):
+            assert a.count(tb, stream=s) == nb                  # 64x longer text, same stream
+            bo = torch.empty(nb + 8, dtype=torch.int64, device="cuda")
+            bp = torch.empty(nb + 8, dtype=torch.int32, device="cuda")
+            bc = torch.zeros(1, dtype=torch.int64, device="cuda")
+            a.match_async(tb, bo, bp, bc, stream=s)
+        torch.cuda.synchronize()
+        assert int(bc.item()) == nb
+        off.fill_(-1)
+        d_count.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        say("replay after larger calls", r)
+        assert int(d_count.item()) == n
+        assert_same((off[:n].cpu().numpy(), pid[:n].cpu().numpy()), exp, f"replay {r}")
 
 
 def test_interleaved_call_kinds_share_a_stream():

@@ -227,3 +227,47 @@ def test_stored_digests_still_match(oracle_lib):
     for w in mg.workloads():
         off, pid = oracle_match(w.keywords, w.text)
         assert stored[w.name] == (len(off), mg.digest(off, pid)), w.name
+
+
+@pytest.mark.parametrize("slice_bytes", [4096, 65536, 1 << 20])
+def test_sliced_oracle_equals_whole(oracle_lib, slice_bytes):
+    """The GPU tests compare their largest texts with the oracle run over
+    overlapping slices on host threads (tests/helpers.py).  Pinned here
+    against the oracle run once over the whole text: sweep keywords on 4 MiB
+    of text with every keyword planted across slice boundaries (starting up
+    to max_len bytes before a boundary and just after it), and the tiny
+    workload."""
+    from tests.helpers import oracle_sliced
+    from workloads import config_sweep
+    w = config_sweep(4 << 20)
+    text = w.text.copy()
+    rng = np.random.default_rng(9)
+    L = max(len(k) for k in w.keywords)
+    for b in range(slice_bytes, len(text) - 64, slice_bytes):
+        for d in (-L, -L + 1, -3, -1, 0, 1):
+            k = w.keywords[int(rng.integers(len(w.keywords)))]
+            o = b + d
+            if 0 <= o <= len(text) - len(k):
+                text[o:o + len(k)] = np.frombuffer(k, dtype=np.uint8)
+    o = Oracle(w.keywords)
+    whole = o.match(text)
+    (got,) = oracle_sliced(o, L, [text], slice_bytes=slice_bytes, workers=4)
+    assert np.array_equal(got[0], whole[0]) and np.array_equal(got[1], whole[1])
+    o.close()
+    t = config_tiny()
+    o = Oracle(t.keywords)
+    whole = o.match(t.text)
+    (got,) = oracle_sliced(o, max(len(k) for k in t.keywords), [t.text], slice_bytes=slice_bytes, workers=4)
+    assert np.array_equal(got[0], whole[0]) and np.array_equal(got[1], whole[1])
+    o.close()
+
+
+def test_sliced_oracle_handles_empty_and_short_texts(oracle_lib):
+    from tests.helpers import oracle_sliced
+    kws = [b"ab", b"abc"]
+    o = Oracle(kws)
+    texts = [np.zeros(0, np.uint8), np.frombuffer(b"a", np.uint8), np.frombuffer(b"abcab", np.uint8)]
+    res = oracle_sliced(o, 3, texts, slice_bytes=2, workers=2)
+    assert len(res[0][0]) == 0 and len(res[1][0]) == 0
+    assert res[2][0].tolist() == [0, 0, 3] and res[2][1].tolist() == [0, 1, 0]
+    o.close()
