@@ -164,6 +164,27 @@ int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len,
                    const ac_matches *matches, const ac_launch *launch,
                    int64_t *d_count, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * scan as ac_match_async, with the filtered policy's hit regions taken from a
+ * fixed array in the library's device code instead of per-stream scratch.
+ * The call makes no hipMalloc, hipFree or other allocating call, on any call,
+ * including the first on a device (which only looks up the array's address
+ * there).  The array holds 16 MiB per GPU for the life of the process: 256
+ * records of 16 bytes for each of the 4096 waves of the widest launch on a
+ * 256-CU MI355X; a launch whose waves would get fewer than 128 records each
+ * is rejected with AC_EINVAL (a wave whose records run out finishes its
+ * share walking hits as it finds them, which is slower, never wrong).  Every
+ * call on one GPU uses that GPU's one array, so two such calls must not
+ * overlap on a GPU (serialise them on one stream, or wait between them);
+ * overlapping calls race on the array and their results are undefined.
+ * Matches, count, launch choices and errors are those of ac_match_async.
+ */
+int ac_match_async_noalloc(const ac_automaton *a, const uint8_t *d_text, int64_t len,
+                           const ac_matches *matches, const ac_launch *launch,
+                           int64_t *d_count, hipStream_t stream);
+
 /* ---- batches -------------------------------------------------------------- */
 typedef struct {
     int32_t *text_id;         /* device [capacity]                              */

@@ -23,7 +23,7 @@ EXPORTS = [
     "ac_match_batch", "ac_match_batch_async", "ac_info", "ac_default_launch",
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
-    "ac_plan_hash2", "ac_tune",
+    "ac_plan_hash2", "ac_tune", "ac_match_async_noalloc",
 ]
 # every symbol include/pfac_serve.h declares
 SERVE_EXPORTS = [
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_match": (i64, [vp, vp, i64, vp, vp]),
         "ac_match_ex": (i64, [vp, vp, i64, vp, vp, vp]),
         "ac_match_async": (ctypes.c_int, [vp, vp, i64, vp, vp, vp, vp]),
+        "ac_match_async_noalloc": (ctypes.c_int, [vp, vp, i64, vp, vp, vp, vp]),
         "ac_match_batch": (i64, [vp, vp, vp, i32, i64, vp, vp, vp]),
         "ac_match_batch_async": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp, vp, vp]),
         "ac_info": (ctypes.c_int, [vp, vp]),

@@ -203,6 +203,19 @@ class Automaton:
                                         ctypes.c_void_p(d_count.data_ptr()), _stream_ptr(stream)),
                 "ac_match_async")
 
+    def match_async_noalloc(self, text, offsets, pattern_ids, d_count, launch: Optional[L.Launch] = None,
+                            stream=None) -> None:
+        """As ``match_async``, with the library's fixed device array as
+        scratch (no device allocation; calls on one GPU must not overlap)."""
+        _check_text(text)
+        m = L.Matches(ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(pattern_ids.data_ptr()),
+                      min(offsets.numel(), pattern_ids.numel()))
+        L.check(L.load().ac_match_async_noalloc(self._h, ctypes.c_void_p(text.data_ptr()), text.numel(),
+                                                ctypes.byref(m),
+                                                ctypes.byref(launch) if launch is not None else None,
+                                                ctypes.c_void_p(d_count.data_ptr()), _stream_ptr(stream)),
+                "ac_match_async_noalloc")
+
     # -- batches -----------------------------------------------------------------
     def match_batch_into(self, texts, text_offsets, text_ids, offsets, pattern_ids, per_text=None,
                          launch: Optional[L.Launch] = None, stream=None, total_bytes: Optional[int] = None) -> int:

@@ -450,7 +450,64 @@ void pfac::release_stream_scratch(hipStream_t stream) {
     g_slots.erase(it);
 }
 
+namespace {
+
+// ---- the allocation-free scan's scratch ----------------------------------
+// Hit regions of ac_match_async_noalloc: a fixed device array that each GPU
+// holds for the life of the process (16 MiB: 4096 waves x 256 records of
+// 16 bytes, the widest launch on a 256-CU MI355X).  In host code `scratch`
+// only names the array; its device address, one per GPU, comes from
+// hipGetSymbolAddress with that GPU current.
+constexpr int64_t kStaticScratchBytes = int64_t(16) << 20;
+// fewest records per region the scan accepts: two drains' worth
+constexpr int64_t kNoallocMinCap = 128;
+static __device__ __align__(256) uint4 scratch[kStaticScratchBytes / sizeof(uint4)];
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+uint4 *g_static_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (set on the first call there).
+int static_scratch(int dev, uint4 **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(AC_EINVAL, "ac_match_async_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail("hipGetSymbolAddress(scratch)", e);
+        if (!p) return fail(AC_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_static_ptr[dev] = static_cast<uint4 *>(p);
+    }
+    *out = g_static_ptr[dev];
+    return AC_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int ac_match_async_noalloc(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,
+                           const ac_launch *launch, int64_t *d_count, hipStream_t stream) {
+    int rc = check_single(a, d_text, len, matches);
+    if (rc) return rc;
+    if ((rc = check_launch(launch))) return rc;
+    if (!d_count) return fail(AC_EINVAL, "ac_match_async_noalloc: NULL count pointer");
+    const ScanArgs S = single_args(d_text, len, matches);
+    const ac_launch cfg = resolved(a, S, launch, false);
+    HitScratch hs;
+    if (cfg.policy == AC_POLICY_FILTERED && len > 0) {
+        const int64_t regions = scan_regions(a, S.text, S.n, cfg);
+        const int64_t cap = std::min<int64_t>(kHitCap, kStaticScratchBytes / int64_t(sizeof(uint4)) / regions);
+        if (cap < kNoallocMinCap)
+            return fail(AC_EINVAL, "ac_match_async_noalloc: the launch needs " + std::to_string(regions) +
+                                       " hit regions of at least " + std::to_string(kNoallocMinCap) +
+                                       " records; the static scratch holds " +
+                                       std::to_string(kStaticScratchBytes) + " bytes");
+        if ((rc = static_scratch(a->device, &hs.hits))) return rc;
+        hs.regions = regions;
+        hs.cap = int32_t(cap);
+    }
+    return enqueue(a, S, cfg, false, true, reinterpret_cast<unsigned long long *>(d_count), hs, stream);
+}
 
 const char *ac_last_error(void) { return g_err.c_str(); }
 
