@@ -214,6 +214,50 @@ int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts,
                          const ac_batch_matches *matches, const ac_launch *launch,
                          int64_t *d_count, hipStream_t stream);
 
+/* ---- CPU matcher and CPU/GPU dispatch --------------------------------------- */
+/*
+ * The paper measures where a GPU starts to beat a serial CPU matcher on the
+ * same input and concludes that an application should switch processing
+ * units automatically around that size (Section IV, Fig. 6-8; Section V).
+ *
+ * ac_match_host: the same match set R as ac_match, computed on host threads
+ * by the failure-less walk over the automaton's own tables (text, offset and
+ * pattern_id are HOST memory).  n_threads <= 0 lets the library choose (one
+ * thread below 1 MiB).  Returns |R| and writes up to `capacity` matches in
+ * unspecified order, like ac_match.  Errors: AC_EINVAL, AC_ENOMEM.
+ * ac_plan_match_host: the same on a host-only build (no GPU needed).
+ */
+int64_t ac_match_host(const ac_automaton *a, const uint8_t *text, int64_t len, int64_t *offset,
+                      int32_t *pattern_id, int64_t capacity, int32_t n_threads);
+int64_t ac_plan_match_host(const ac_plan *p, const uint8_t *text, int64_t len, int64_t *offset,
+                           int32_t *pattern_id, int64_t capacity, int32_t n_threads);
+
+#define AC_RAN_CPU 1
+#define AC_RAN_GPU 2
+/*
+ * Host text in, host matches out, on whichever unit finishes first: texts
+ * shorter than the automaton's dispatch threshold go to ac_match_host, the
+ * others are copied to the device (per-stream staging, grown as needed),
+ * scanned and their matches copied back, all on `stream`, which the call
+ * synchronises.  *ran_on (may be NULL) receives AC_RAN_CPU or AC_RAN_GPU.
+ * Returns |R| as ac_match does.  Errors: AC_EINVAL, AC_ENOMEM, AC_EHIP.
+ */
+int64_t ac_match_dispatch(const ac_automaton *a, const uint8_t *text, int64_t len, int64_t *offset,
+                          int32_t *pattern_id, int64_t capacity, hipStream_t stream, int32_t *ran_on);
+/* Sets the dispatch threshold in bytes (negative: the built-in 8 KiB). */
+int ac_set_dispatch_threshold(ac_automaton *a, int64_t bytes);
+int64_t ac_dispatch_threshold(const ac_automaton *a);
+/*
+ * Measures the crossover on prefixes of a host sample (512 B, 1 KiB, ...,
+ * up to min(len, 64 MiB)): the median of 7 timed calls each way, the CPU
+ * matcher against the GPU round trip of ac_match_dispatch, and sets the
+ * threshold to the first size where the GPU is faster (twice the largest
+ * size tried if it never is).  *threshold (may be NULL) receives it.
+ * Synchronises `stream`.  Errors: AC_EINVAL (len < 512), AC_ENOMEM, AC_EHIP.
+ */
+int ac_calibrate_dispatch(ac_automaton *a, const uint8_t *sample, int64_t len, hipStream_t stream,
+                          int64_t *threshold);
+
 /* ---- introspection ---------------------------------------------------------- */
 typedef struct {
     int32_t n_patterns;

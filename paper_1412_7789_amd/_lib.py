@@ -24,7 +24,10 @@ EXPORTS = [
     "ac_last_error", "ac_compile", "ac_plan_info", "ac_plan_export", "ac_plan_hash",
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
     "ac_plan_hash2", "ac_tune", "ac_match_async_noalloc",
+    "ac_match_host", "ac_plan_match_host", "ac_match_dispatch", "ac_set_dispatch_threshold",
+    "ac_dispatch_threshold", "ac_calibrate_dispatch",
 ]
+AC_RAN_CPU, AC_RAN_GPU = 1, 2
 # every symbol include/pfac_serve.h declares
 SERVE_EXPORTS = [
     "ac_server_create", "ac_server_destroy", "ac_server_add_automaton", "ac_server_submit",
@@ -122,6 +125,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_match_ex": (i64, [vp, vp, i64, vp, vp, vp]),
         "ac_match_async": (ctypes.c_int, [vp, vp, i64, vp, vp, vp, vp]),
         "ac_match_async_noalloc": (ctypes.c_int, [vp, vp, i64, vp, vp, vp, vp]),
+        "ac_match_host": (i64, [vp, vp, i64, vp, vp, i64, i32]),
+        "ac_plan_match_host": (i64, [vp, vp, i64, vp, vp, i64, i32]),
+        "ac_match_dispatch": (i64, [vp, vp, i64, vp, vp, i64, vp, vp]),
+        "ac_set_dispatch_threshold": (ctypes.c_int, [vp, i64]),
+        "ac_dispatch_threshold": (i64, [vp]),
+        "ac_calibrate_dispatch": (ctypes.c_int, [vp, vp, i64, vp, vp]),
         "ac_match_batch": (i64, [vp, vp, vp, i32, i64, vp, vp, vp]),
         "ac_match_batch_async": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp, vp, vp]),
         "ac_info": (ctypes.c_int, [vp, vp]),

@@ -67,6 +67,28 @@ def _opts(dense_budget_bytes: int, hash_multiplier: int) -> L.BuildOpts:
     return o
 
 
+def _host_bytes(text) -> np.ndarray:
+    buf = np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray)) else np.asarray(text)
+    if buf.dtype != np.uint8 or buf.ndim != 1:
+        raise TypeError("host text must be a 1-D uint8 array or bytes")
+    return np.ascontiguousarray(buf)
+
+
+def _host_call(fn, h, text, capacity, *tail):
+    """Runs a host-output matcher call, growing the output arrays once if the
+    first capacity was too small; returns (offsets, pattern_ids, count)."""
+    buf = _host_bytes(text)
+    cap = capacity if capacity is not None else max(256, buf.size // 8)
+    while True:
+        off = np.empty(max(cap, 1), dtype=np.int64)
+        pid = np.empty(max(cap, 1), dtype=np.int32)
+        n = L.check(fn(h, buf.ctypes.data if buf.size else None, buf.size, off.ctypes.data, pid.ctypes.data,
+                       cap, *tail), fn.__name__)
+        if n <= cap:
+            return off[:n], pid[:n], n
+        cap = n
+
+
 class Plan:
     """Host-side build result (``ac_compile``): tables for inspection, no GPU."""
 
@@ -101,6 +123,11 @@ class Plan:
         b1, b2 = ctypes.c_uint32(), ctypes.c_uint32()
         L.load().ac_plan_prefix_buckets(self._h, x & 0xFFFFFFFF, ctypes.byref(b1), ctypes.byref(b2))
         return b1.value, b2.value
+
+    def match_host(self, text, n_threads: int = 0, capacity: Optional[int] = None):
+        """The library's CPU matcher (no GPU): host (offsets, pattern_ids)."""
+        off, pid, _ = _host_call(L.load().ac_plan_match_host, self._h, text, capacity, n_threads)
+        return off, pid
 
     def close(self) -> None:
         if self._h:
@@ -215,6 +242,37 @@ class Automaton:
                                                 ctypes.byref(launch) if launch is not None else None,
                                                 ctypes.c_void_p(d_count.data_ptr()), _stream_ptr(stream)),
                 "ac_match_async_noalloc")
+
+    # -- CPU matcher and CPU/GPU dispatch ---------------------------------------
+    def match_host(self, text, n_threads: int = 0, capacity: Optional[int] = None):
+        """Host text -> host (offsets, pattern_ids) on the library's CPU matcher."""
+        off, pid, _ = _host_call(L.load().ac_match_host, self._h, text, capacity, n_threads)
+        return off, pid
+
+    def match_dispatch(self, text, capacity: Optional[int] = None, stream=None):
+        """Host text -> host (offsets, pattern_ids, ran_on) on the CPU below the
+        dispatch threshold, else on the GPU (ran_on: AC_RAN_CPU / AC_RAN_GPU)."""
+        ran = ctypes.c_int32(0)
+        off, pid, _ = _host_call(L.load().ac_match_dispatch, self._h, text, capacity, _stream_ptr(stream),
+                                 ctypes.byref(ran))
+        return off, pid, ran.value
+
+    @property
+    def dispatch_threshold(self) -> int:
+        return int(L.check(L.load().ac_dispatch_threshold(self._h), "ac_dispatch_threshold"))
+
+    @dispatch_threshold.setter
+    def dispatch_threshold(self, nbytes: int) -> None:
+        L.check(L.load().ac_set_dispatch_threshold(self._h, int(nbytes)), "ac_set_dispatch_threshold")
+
+    def calibrate_dispatch(self, sample, stream=None) -> int:
+        """Measures the CPU/GPU crossover on prefixes of a host sample and sets
+        the dispatch threshold to it; returns the threshold."""
+        buf = _host_bytes(sample)
+        thr = ctypes.c_int64(0)
+        L.check(L.load().ac_calibrate_dispatch(self._h, buf.ctypes.data, buf.size, _stream_ptr(stream),
+                                               ctypes.byref(thr)), "ac_calibrate_dispatch")
+        return thr.value
 
     # -- batches -----------------------------------------------------------------
     def match_batch_into(self, texts, text_offsets, text_ids, offsets, pattern_ids, per_text=None,

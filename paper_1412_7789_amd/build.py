@@ -7,13 +7,16 @@ from the shell.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpfac.so")
-SOURCES = ["plan.cpp", "kernels.hip", "capi.cpp", "serve.cpp"]
+# the filtered kernels of each stride compile in their own unit, in parallel
+SOURCES = ["filtered_s1k1.hip", "filtered_s1k2.hip", "filtered_s1k3.hip", "filtered_s2.hip", "filtered_s4.hip",
+           "kernels.hip", "plan.cpp", "capi.cpp", "serve.cpp", "host_match.cpp"]
 ARCH = os.environ.get("PFAC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -31,23 +34,26 @@ def build(out: str = LIB, verbose: bool = False) -> str:
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+
+    def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc, *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *lang, "-c",
+        cmd = [hipcc, *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-x", "hip", "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
         warn = "\n".join(l for l in (res.stderr or "").splitlines()
                          if "packed-fp32-ops" not in l and "target-feature" not in l
                          and l.strip() and "warning generated" not in l)
-        if res.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")
         if verbose and warn:
             print(warn, file=sys.stderr)
-        objs.append(obj)
+        return obj
+
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     subprocess.run(cmd, check=True, capture_output=not verbose)

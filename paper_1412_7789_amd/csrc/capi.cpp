@@ -9,7 +9,9 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <system_error>
 #include <utility>
+#include <vector>
 
 #include "pfac_internal.hpp"
 
@@ -46,6 +48,12 @@ struct CountSlot {
     bool stale = false;                        // a failed call may have left *d != *h
     hipEvent_t ev[2] = {nullptr, nullptr};   // kernel timing: scan start, stop
     HitScratch hs;                             // hit regions of the filtered policy
+    // ac_match_dispatch's device staging, grown to the largest call
+    uint8_t *d_text = nullptr;
+    int64_t text_cap = 0;
+    int64_t *d_off = nullptr;
+    int32_t *d_pid = nullptr;
+    int64_t match_cap = 0;
 };
 std::mutex g_slots_mu;
 std::map<std::pair<int, hipStream_t>, CountSlot> g_slots;
@@ -56,7 +64,35 @@ void free_slot(CountSlot &s) {
     for (hipEvent_t ev : s.ev)
         if (ev) (void)hipEventDestroy(ev);
     if (s.hs.hits) (void)hipFree(s.hs.hits);
+    for (void *p : {static_cast<void *>(s.d_text), static_cast<void *>(s.d_off), static_cast<void *>(s.d_pid)})
+        if (p) (void)hipFree(p);
     s = CountSlot();
+}
+
+// Grows the slot's dispatch staging to `text` bytes and `matches` entries.
+int ensure_staging(CountSlot &s, int64_t text, int64_t matches) {
+    hipError_t e = hipSuccess;
+    if (text > s.text_cap) {
+        const int64_t cap = std::max<int64_t>(text, 2 * s.text_cap);
+        if (s.d_text) (void)hipFree(s.d_text);
+        s.d_text = nullptr;
+        s.text_cap = 0;
+        if ((e = hipMalloc(reinterpret_cast<void **>(&s.d_text), size_t(cap))) != hipSuccess)
+            return fail(AC_ENOMEM, std::string("hipMalloc(dispatch text): ") + hipGetErrorString(e));
+        s.text_cap = cap;
+    }
+    if (matches > s.match_cap) {
+        if (s.d_off) (void)hipFree(s.d_off);
+        if (s.d_pid) (void)hipFree(s.d_pid);
+        s.d_off = nullptr;
+        s.d_pid = nullptr;
+        s.match_cap = 0;
+        if ((e = hipMalloc(reinterpret_cast<void **>(&s.d_off), size_t(matches) * 8)) != hipSuccess ||
+            (e = hipMalloc(reinterpret_cast<void **>(&s.d_pid), size_t(matches) * 4)) != hipSuccess)
+            return fail(AC_ENOMEM, std::string("hipMalloc(dispatch matches): ") + hipGetErrorString(e));
+        s.match_cap = matches;
+    }
+    return AC_OK;
 }
 
 // The slot of (device, stream), created on first use with hit regions for
@@ -402,6 +438,57 @@ ScanArgs batch_args(const uint8_t *d_texts, const int64_t *d_off, int32_t n_text
     return S;
 }
 
+int check_host(const void *h, const uint8_t *text, int64_t len, int64_t *off, int32_t *pid, int64_t cap,
+               const char *who) {
+    if (!h) return fail(AC_EINVAL, std::string(who) + ": NULL automaton");
+    if (len < 0) return fail(AC_EINVAL, std::string(who) + ": negative length");
+    if (len > 0 && !text) return fail(AC_EINVAL, std::string(who) + ": NULL text");
+    if (cap < 0) return fail(AC_EINVAL, std::string(who) + ": negative capacity");
+    if (cap > 0 && (!off || !pid)) return fail(AC_EINVAL, std::string(who) + ": NULL match arrays");
+    return AC_OK;
+}
+
+int64_t host_match_checked(const Plan &P, const uint8_t *text, int64_t len, int64_t *off, int32_t *pid,
+                           int64_t cap, int32_t n_threads) {
+    try {
+        return host_match(P, text, len, off, pid, cap, n_threads);
+    } catch (const std::bad_alloc &) {
+        return fail(AC_ENOMEM, "CPU matcher: out of host memory");
+    } catch (const std::system_error &e) {
+        return fail(AC_ENOMEM, std::string("CPU matcher: cannot start threads: ") + e.what());
+    }
+}
+
+// GPU side of the dispatch: host text -> device, scan, matches -> host.
+int64_t gpu_round_trip(const ac_automaton *a, const uint8_t *text, int64_t len, int64_t *off, int32_t *pid,
+                       int64_t cap, hipStream_t stream) {
+    if (len == 0) return 0;
+    CountSlot *slot = nullptr;
+    int rc = slot_for(a, stream, &slot);
+    if (rc) return rc;
+    if ((rc = ensure_staging(*slot, len, std::max<int64_t>(cap, 1)))) return rc;
+    hipError_t e = hipMemcpyAsync(slot->d_text, text, size_t(len), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail("hipMemcpyAsync(dispatch text)", e);
+    ScanArgs S{};
+    S.text = slot->d_text;
+    S.n = len;
+    if (cap > 0) {
+        S.out_off = slot->d_off;
+        S.out_pid = slot->d_pid;
+        S.cap = cap;
+    }
+    const int64_t count = sync_count(a, S, nullptr, false, stream);
+    if (count < 0) return count;
+    const int64_t put = std::min(count, cap);
+    if (put > 0) {
+        if ((e = hipMemcpyAsync(off, slot->d_off, size_t(put) * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(pid, slot->d_pid, size_t(put) * 4, hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return hip_fail("hipMemcpyAsync(dispatch matches)", e);
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail("hipStreamSynchronize", e);
+    }
+    return count;
+}
+
 int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const ac_build_opts *opts,
                  ac_automaton **out) {
     if (!out) return fail(AC_EINVAL, "ac_build: NULL output pointer");
@@ -690,6 +777,88 @@ int ac_match_batch_async(const ac_automaton *a, const uint8_t *d_texts, const in
     CountSlot *slot = nullptr;
     if ((rc = slot_for(a, stream, &slot))) return rc;
     return enqueue(a, S, cfg, true, true, reinterpret_cast<unsigned long long *>(d_count), slot->hs, stream);
+}
+
+// ---- CPU matcher and CPU/GPU dispatch ------------------------------------------
+int64_t ac_match_host(const ac_automaton *a, const uint8_t *text, int64_t len, int64_t *offset,
+                      int32_t *pattern_id, int64_t capacity, int32_t n_threads) {
+    int rc = check_host(a, text, len, offset, pattern_id, capacity, "ac_match_host");
+    if (rc) return rc;
+    return host_match_checked(a->host, text, len, offset, pattern_id, capacity, n_threads);
+}
+
+int64_t ac_plan_match_host(const ac_plan *p, const uint8_t *text, int64_t len, int64_t *offset,
+                           int32_t *pattern_id, int64_t capacity, int32_t n_threads) {
+    int rc = check_host(p, text, len, offset, pattern_id, capacity, "ac_plan_match_host");
+    if (rc) return rc;
+    return host_match_checked(p->p, text, len, offset, pattern_id, capacity, n_threads);
+}
+
+int64_t ac_match_dispatch(const ac_automaton *a, const uint8_t *text, int64_t len, int64_t *offset,
+                          int32_t *pattern_id, int64_t capacity, hipStream_t stream, int32_t *ran_on) {
+    int rc = check_host(a, text, len, offset, pattern_id, capacity, "ac_match_dispatch");
+    if (rc) return rc;
+    if (len < a->dispatch_bytes.load(std::memory_order_relaxed)) {
+        if (ran_on) *ran_on = AC_RAN_CPU;
+        return host_match_checked(a->host, text, len, offset, pattern_id, capacity, 0);
+    }
+    if ((rc = device_matches(a))) return rc;
+    if (ran_on) *ran_on = AC_RAN_GPU;
+    return gpu_round_trip(a, text, len, offset, pattern_id, capacity, stream);
+}
+
+int ac_set_dispatch_threshold(ac_automaton *a, int64_t bytes) {
+    if (!a) return fail(AC_EINVAL, "ac_set_dispatch_threshold: NULL automaton");
+    a->dispatch_bytes.store(bytes < 0 ? kDefaultDispatchBytes : bytes, std::memory_order_relaxed);
+    return AC_OK;
+}
+
+int64_t ac_dispatch_threshold(const ac_automaton *a) {
+    if (!a) return fail(AC_EINVAL, "ac_dispatch_threshold: NULL automaton");
+    return a->dispatch_bytes.load(std::memory_order_relaxed);
+}
+
+int ac_calibrate_dispatch(ac_automaton *a, const uint8_t *sample, int64_t len, hipStream_t stream,
+                          int64_t *threshold) {
+    int rc = check_host(a, sample, len, nullptr, nullptr, 0, "ac_calibrate_dispatch");
+    if (rc) return rc;
+    if (len < 512) return fail(AC_EINVAL, "ac_calibrate_dispatch: sample shorter than 512 bytes");
+    if ((rc = device_matches(a))) return rc;
+    // prefixes of 512 B x 2^k: medians of 7 runs each way (after one warm-up)
+    const int64_t top = std::min<int64_t>(len, int64_t(64) << 20);
+    std::vector<int64_t> off;
+    std::vector<int32_t> pid;
+    auto median_ms = [&](auto &&run) -> double {
+        std::vector<double> t;
+        for (int r = 0; r < 8; ++r) {
+            const auto t0 = std::chrono::steady_clock::now();
+            const int64_t c = run();
+            const auto t1 = std::chrono::steady_clock::now();
+            if (c < 0) return -1.0;
+            if (r) t.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        std::sort(t.begin(), t.end());
+        return t[t.size() / 2];
+    };
+    int64_t found = -1;
+    for (int64_t n = 512; n <= top; n *= 2) {
+        const int64_t cap = a->host.n_patterns > 0 ? n * 4 + 64 : 64;
+        off.resize(size_t(cap));
+        pid.resize(size_t(cap));
+        const double cpu = median_ms([&] { return host_match_checked(a->host, sample, n, off.data(), pid.data(), cap, 0); });
+        const double gpu = median_ms([&] { return gpu_round_trip(a, sample, n, off.data(), pid.data(), cap, stream); });
+        if (cpu < 0 || gpu < 0) return AC_EHIP;
+        if (gpu < cpu) {
+            found = n;
+            break;
+        }
+        if (n > top / 2) break;
+    }
+    // the GPU never won within the sample: everything up to it stays on the CPU
+    if (found < 0) found = top * 2;
+    a->dispatch_bytes.store(found, std::memory_order_relaxed);
+    if (threshold) *threshold = found;
+    return AC_OK;
 }
 
 // ---- host-side inspection -----------------------------------------------------

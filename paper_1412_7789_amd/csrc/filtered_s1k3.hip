@@ -1,0 +1,8 @@
+// Filtered-scan kernels of stride 1, prefix length 3 (see filtered.hpp).
+#include "filtered.hpp"
+
+namespace pfac {
+
+dev::FilteredFn pick_filtered_s1k3(int kind, int segs) { return dev::pick_filter<3, 1>(kind, segs); }
+
+}  // namespace pfac

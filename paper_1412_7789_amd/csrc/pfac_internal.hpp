@@ -2,6 +2,7 @@
 // HIP kernels of the failure-less Aho-Corasick matcher.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <mutex>
@@ -21,6 +22,10 @@ constexpr uint32_t kDefaultHashMul = 0x9E3779u;   // odd 24-bit multiplier
 constexpr uint32_t kPrefixMul2 = 0x5BD1E5u;       // second bucket of the prefix table
 constexpr int64_t kDefaultDenseBudget = 64ll << 20;
 constexpr int32_t kFinalBit = int32_t(0x80000000u);
+// ac_match_dispatch's CPU/GPU crossover before ac_calibrate_dispatch or
+// ac_set_dispatch_threshold sets one (measured on MI355X with its host CPU:
+// 1000 printable keywords, text in pinned host memory)
+constexpr int64_t kDefaultDispatchBytes = int64_t(8) << 10;
 
 // Filter geometry: index bits taken from the top of the 32-bit product.
 struct FilterGeom {
@@ -153,6 +158,8 @@ struct ac_automaton {
     // launch choices measured by ac_tune, by text-length bucket (floor(log4 len))
     mutable std::mutex tune_mu;
     std::map<int, ac_launch> tuned;
+    // texts shorter than this go to the CPU matcher in ac_match_dispatch
+    std::atomic<int64_t> dispatch_bytes{pfac::kDefaultDispatchBytes};
 };
 
 namespace pfac {
@@ -170,6 +177,12 @@ struct HitScratch {
     int32_t cap = 0;
 };
 constexpr int32_t kHitCap = 1024;
+
+// host_match.cpp: every (offset, keyword id) of text[0, n) found on host
+// threads (n_threads <= 0: chosen by length); writes up to cap of them and
+// returns how many there are.
+int64_t host_match(const Plan &P, const uint8_t *text, int64_t n, int64_t *off, int32_t *pid, int64_t cap,
+                   int32_t n_threads);
 
 // kernels.hip
 int64_t scan_regions(const ac_automaton *a, const uint8_t *text, int64_t n, const ac_launch &cfg);
