@@ -9,14 +9,16 @@ synchronous return of the exact count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Prints ONE JSON line: text GB/s (1 GB = 1e9 B); the roofline of the scan
-kernel (text read + matches written per launch / its duration from HIP
-events, against the 8 TB/s HBM peak; HBM traffic from the stored rocprofv3
-counters while the device code is unchanged); the achievable read bandwidth
-of the same buffer from a streaming-read probe; the CPU oracle timed on a
-bounded sample; and, for the default workload, the batched (4096 texts) and
+Prints ONE JSON line: text GB/s (1 GB = 1e9 B) with p10/p50/p90 step times;
+the roofline of the scan kernel (text read + matches written per launch /
+its duration from HIP events, against the 8 TB/s HBM peak; HBM traffic from
+the stored rocprofv3 counters while the device code is unchanged); the
+achievable read bandwidth of the same buffer from a streaming-read probe; the
+CPU oracle timed on a bounded sample, pinned to one core; and, for the
+default workload, the 20000-keyword 1 GiB scan, the batched (4096 texts) and
 served (request trace at 1x and 4x the arrival rate) figures against their
-plain forms.
+plain forms, the CPU/GPU crossover over the 1000-keyword workload's sizes
+(the paper's question) and the CPU/GPU dispatch against either unit alone.
 
     python bench.py --workload batched | served | crossover | large_1g | tiny
 
@@ -35,7 +37,9 @@ import argparse
 import hashlib
 import json
 import os
+import shutil
 import struct
+import subprocess
 import sys
 import time
 
@@ -46,7 +50,7 @@ METRIC = "text GB/s scanned (exact matches); batched/served GB/s + p50/p99 vs pl
 HBM_PEAK_GBPS = 8000.0
 LIB_FILE = os.path.join(ROOT, "paper_1412_7789_amd", "libpfac.so")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-GIB = 1 << 30
+KIB, MIB, GIB = 1 << 10, 1 << 20, 1 << 30
 
 
 def log(*a):
@@ -61,6 +65,7 @@ def kernel_sha() -> str:
         elf = f.read()
     shoff, = struct.unpack_from("<Q", elf, 0x28)
     shentsize, shnum, shstrndx = struct.unpack_from("<HHH", elf, 0x3A)
+
     def section(i):
         name, _type, _flags, _addr, off, size = struct.unpack_from("<IIQQQQ", elf, shoff + i * shentsize)
         return name, off, size
@@ -105,10 +110,139 @@ def make_workload(name: str):
     return w, desc
 
 
+def pct(xs, q):
+    import numpy as np
+    return round(float(np.percentile(np.asarray(xs, dtype=float), q)), 4)
+
+
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle (serial Goto/Failure/Output Aho-Corasick), match
+# phase only, in a child process pinned to one core with taskset before any
+# GPU work has started.
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        return [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+    except (OSError, IndexError):
+        return "unknown"
+
+
+def cpu_baseline_child(workload: str, sample_mib: int, reps: int) -> None:
+    """Runs in the pinned child: prints the oracle's match times on the first
+    sample_mib MiB of the workload's text."""
+    from oracle import Oracle
+    w, _ = make_workload(workload)
+    sample = w.text[:min(len(w.text), sample_mib << 20)]
+    o = Oracle(w.keywords)
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        o.match(sample)
+        times.append(time.perf_counter() - t0)
+    o.close()
+    print(json.dumps({"sample_bytes": len(sample), "runs_s": times,
+                      "affinity": sorted(os.sched_getaffinity(0))}), flush=True)
+
+
+def cpu_baseline(workload: str, sample_mib: int, reps: int) -> dict:
+    cpus = sorted(os.sched_getaffinity(0))
+    core = cpus[-1]
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-child", "--workload", workload,
+           "--cpu-sample-mib", str(sample_mib), "--cpu-reps", str(reps)]
+    pinned_with = "taskset"
+    if shutil.which("taskset"):
+        cmd = ["taskset", "-c", str(core)] + cmd
+    else:
+        pinned_with = "sched_setaffinity"
+        cmd += ["--cpu-core", str(core)]
+    log(f"[bench] cpu baseline: oracle on {sample_mib} MiB x {reps}, core {core} ({pinned_with})")
+    res = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    if res.returncode != 0:
+        raise RuntimeError(f"cpu baseline child failed: {res.stderr[-2000:]}")
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    import numpy as np
+    med = float(np.median(r["runs_s"]))
+    model = cpu_model()
+    return {"value": round(r["sample_bytes"] / med / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {r['sample_bytes'] >> 20} MiB of the same text, serial Aho-Corasick "
+                      f"(Goto/Failure/Output), match phase only, median of {reps} runs "
+                      f"({', '.join(f'{x:.2f}' for x in r['runs_s'])} s), one thread pinned to core "
+                      f"{r['affinity']} with {pinned_with}, on {model}",
+            "runs_s": [round(x, 3) for x in r["runs_s"]], "nproc": len(cpus), "cpu_count": os.cpu_count(),
+            "model": model}
+
+
+# --------------------------------------------------------------------------
+def bench_single(pf, torch, np, dev, name: str, steps: int, warmup: int) -> dict:
+    """One workload at 1 GiB (or the tiny one): K synchronous calls over the
+    text already in HBM, timed as a whole and one by one; then K more with
+    HIP events from the scan kernel's dispatch packet for the kernel time."""
+    t = time.time()
+    w, desc = make_workload(name)
+    n = len(w.text)
+    log(f"[bench] workload {name}: {n} bytes, {len(w.keywords)} keywords, gen {time.time() - t:.1f}s")
+    a = pf.Automaton(w.keywords)
+    info = a.info()
+    launch = a.default_launch(n)
+    log(f"[bench] automaton: {info['n_states']} states, {info['n_classes']} classes, "
+        f"build {info['build_ms']:.1f} ms, launch {launch}")
+    host = torch.from_numpy(w.text)
+    # two device copies, each larger than the 256 MB last-level cache, used in turn
+    bufs = [host.to(dev), host.to(dev)]
+    count = a.count(bufs[0])
+    d_off = torch.empty(max(1, count), dtype=torch.int64, device=dev)
+    d_pid = torch.empty(max(1, count), dtype=torch.int32, device=dev)
+    timed_cfg = pf.launch_config(flags=pf.AC_LAUNCH_TIME_SCAN)
+    for i in range(warmup):
+        assert a.match_into(bufs[i % 2], d_off, d_pid) == count
+    torch.cuda.synchronize()
+    per_step = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s0 = time.perf_counter()
+        got = a.match_into(bufs[i % 2], d_off, d_pid)     # synchronous: returns with the final count
+        per_step.append((time.perf_counter() - s0) * 1e3)
+        assert got == count
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    # kernel durations from the scan kernel's own dispatch packet, after the
+    # timed region (reading the events back costs the host ~35 us per call)
+    kern = []
+    for i in range(steps):
+        assert a.match_into(bufs[i % 2], d_off, d_pid, launch=timed_cfg) == count
+        kern.append(pf.last_scan_ms())
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean(kern))
+    log(f"[bench] {name}: {ms_per_step:.4f} ms/step (p10 {pct(per_step, 10)} p90 {pct(per_step, 90)}), "
+        f"kernel {kernel_ms:.4f} ms, {count} matches")
+    alg = n + 12 * count
+    achieved = alg / (kernel_ms * 1e-3) / 1e9
+    out = {"workload": f"{name}: {desc}", "text_bytes": n, "keywords": len(w.keywords), "matches": count,
+           "states": info["n_states"], "classes": info["n_classes"], "launch": launch,
+           "gbps": round(n / (ms_per_step * 1e-3) / 1e9, 2), "ms_per_step": round(ms_per_step, 4),
+           "step_ms_p10_p50_p90": [pct(per_step, 10), pct(per_step, 50), pct(per_step, 90)],
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(name),
+                        "kernel": "filtered_kernel" if launch["policy"] == 1 else "direct_kernel",
+                        "kernel_ms": round(kernel_ms, 4),
+                        "kernel_ms_p10_p90": [pct(kern, 10), pct(kern, 90)],
+                        "kernel_timing": f"HIP events from the scan kernel's dispatch packet, mean of {steps} "
+                                         "steps run right after the timed region",
+                        "algorithmic_bytes_per_launch": alg},
+           "build_ms": round(info["build_ms"], 2)}
+    return out, w, a, bufs, host
+
+
 def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
     """4096 uneven texts (2000 printable keywords): one batched call per step,
-    the same call replayed from a captured HIP graph, and the plain way, one
-    synchronous call per text."""
+    the same call replayed from a captured HIP graph, the batched call after
+    ac_tune_batch, and the plain way, one synchronous call per text."""
     from workloads import config_batched
     t = time.time()
     w = config_batched()
@@ -139,7 +273,7 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
     def batched(i):
         assert a.match_batch_into(d_texts, d_offs, tid, off, pid, per) == count
     ms_batch = timed(batched, steps)
-
+    launch_default = None
     # graph: capture the asynchronous batch call on a stream of its own
     s = torch.cuda.Stream()
     d_count = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -154,7 +288,9 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
         g.replay()
         assert int(d_count.item()) == count
     ms_graph = timed(replay, steps)
-
+    # the autotuner's choice for this batch
+    tuned = a.tune_batch(d_texts, d_offs)
+    ms_tuned = timed(batched, steps)
     # plain: one synchronous call per text (views into the same device buffer)
     bounds = [(int(w.offsets[i]), int(w.offsets[i + 1])) for i in range(n_texts)]
     views = [d_texts[b0:b1] for b0, b1 in bounds]
@@ -166,16 +302,17 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
         assert got == count
     ms_plain = timed(plain, max(1, steps // 10))
     gbps = lambda ms: total / (ms * 1e-3) / 1e9
-    log(f"[bench] batched: {ms_batch:.3f} ms/batch ({gbps(ms_batch):.0f} GB/s), graph {ms_graph:.3f} ms "
-        f"({gbps(ms_graph):.0f} GB/s), per-text calls {ms_plain:.2f} ms ({gbps(ms_plain):.1f} GB/s)")
+    log(f"[bench] batched: {ms_batch:.3f} ms/batch ({gbps(ms_batch):.0f} GB/s), graph {ms_graph:.3f} ms, "
+        f"tuned {ms_tuned:.3f} ms {tuned}, per-text calls {ms_plain:.2f} ms ({gbps(ms_plain):.1f} GB/s)")
     return {"workload": f"{n_texts} texts, log-normal lengths (median 8 KiB, sigma 2.1, clipped to 64 B..4 MiB), "
                         "2000 printable keywords |k| 8..32, Poisson plants 1 per 4 KiB; seed 0",
             "texts": n_texts, "bytes": total, "matches": count,
             "batched_gbps": round(gbps(ms_batch), 2), "batched_ms": round(ms_batch, 4),
             "graph_gbps": round(gbps(ms_graph), 2), "graph_ms": round(ms_graph, 4),
+            "tuned_gbps": round(gbps(ms_tuned), 2), "tuned_ms": round(ms_tuned, 4), "tuned_launch": tuned,
             "plain_gbps": round(gbps(ms_plain), 3), "plain_ms": round(ms_plain, 3),
             "plain": "one synchronous ac_match per text from Python",
-            "speedup_vs_plain": round(ms_plain / ms_batch, 1)}
+            "speedup_vs_plain": round(ms_plain / min(ms_batch, ms_tuned), 1)}
 
 
 def bench_served(pf, torch, np, dev, rate_scale: float = 1.0) -> dict:
@@ -227,17 +364,153 @@ def bench_served(pf, torch, np, dev, rate_scale: float = 1.0) -> dict:
     return out
 
 
-def bench_crossover(pf, torch, np, dev, reps: int = 7) -> dict:
-    """The paper's question (Section IV): from what text size does the GPU
-    beat the serial CPU matcher?  Paper workload (permutations of a..z over
-    131-byte alphabet lines) at the paper's sizes, k x 16375 B and k x 1310 B
-    for k = 1..41.  GPU end-to-end = pinned host->device copy of the text +
-    synchronous match + copy of the matches back; CPU = the oracle's serial
-    match phase (its CPU-baseline role), one thread."""
+def pinned_oracle_ms(o, text, reps: int, core: int):
+    """The oracle's serial match time on `text` (median of reps), this thread
+    pinned to one core while it runs."""
+    import numpy as np
+    before = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {core})
+    try:
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            o.match(text)
+            ts.append((time.perf_counter() - t0) * 1e3)
+    finally:
+        os.sched_setaffinity(0, before)
+    return float(np.median(ts))
+
+
+def gpu_end_to_end(pf, torch, np, a, host, d_text, d_off, d_pid, h_off, h_pid, n, reps, timed_cfg):
+    """Pinned host text -> device, synchronous match, matches -> pinned host:
+    median, p10, p90 of the wall time, and the median scan-kernel time."""
+    tg, tk = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d_text[:n].copy_(host[:n], non_blocking=True)
+        cnt = a.match_into(d_text[:n], d_off, d_pid, launch=timed_cfg)
+        h_off[:cnt].copy_(d_off[:cnt], non_blocking=True)
+        h_pid[:cnt].copy_(d_pid[:cnt], non_blocking=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if r:
+            tg.append((t1 - t0) * 1e3)
+            tk.append(pf.last_scan_ms())
+    return float(np.median(tg)), pct(tg, 10), pct(tg, 90), float(np.median(tk)), cnt
+
+
+def bench_crossover_sweep(pf, torch, np, dev, w, a) -> dict:
+    """The paper's question on this build's own workload: from what text size
+    does the GPU beat the serial CPU matcher?  Sizes of the 1000-keyword
+    workload's sweep (1 KiB, 16 KiB, ... in x16 steps) until the CPU is far
+    behind, then x2 steps between the last size the CPU won and the first
+    it lost; end-to-end (pinned H2D + synchronous match + D2H of the matches)
+    and kernel-only.  CPU = the oracle, one thread pinned to one core."""
+    from oracle import Oracle
+    core = sorted(os.sched_getaffinity(0))[-1]
+    text = w.text
+    host = torch.from_numpy(text[:64 * MIB]).pin_memory()
+    d_text = torch.empty(64 * MIB, dtype=torch.uint8, device=dev)
+    cap = 64 * MIB // 64
+    d_off = torch.empty(cap, dtype=torch.int64, device=dev)
+    d_pid = torch.empty(cap, dtype=torch.int32, device=dev)
+    h_off = torch.empty(cap, dtype=torch.int64).pin_memory()
+    h_pid = torch.empty(cap, dtype=torch.int32).pin_memory()
+    timed_cfg = pf.launch_config(flags=pf.AC_LAUNCH_TIME_SCAN)
+    o = Oracle(w.keywords)
+    points = {}
+
+    def measure(n):
+        if n in points:
+            return points[n]
+        reps = 50 if n <= 4 * MIB else 10
+        g, g10, g90, k, cnt = gpu_end_to_end(pf, torch, np, a, host, d_text, d_off, d_pid, h_off, h_pid, n, reps,
+                                              timed_cfg)
+        c = pinned_oracle_ms(o, text[:n], 5 if n <= 4 * MIB else 3, core)
+        points[n] = {"gpu_end_to_end_ms": round(g, 4), "gpu_p10_p90_ms": [g10, g90], "gpu_kernel_ms": round(k, 4),
+                     "cpu_ms": round(c, 4), "matches": int(cnt)}
+        return points[n]
+
+    sizes = [KIB * 16 ** i for i in range(5)]            # 1 KiB .. 64 MiB
+    for n in sizes:
+        p = measure(n)
+        if n >= 256 * KIB and p["cpu_ms"] > 20 * p["gpu_end_to_end_ms"]:
+            break
+
+    def first_win(key):
+        ns = sorted(points)
+        for i, n in enumerate(ns):
+            if points[n][key] < points[n]["cpu_ms"]:
+                return n, (ns[i - 1] if i else None)
+        return None, None
+
+    out = {}
+    for key, label in (("gpu_end_to_end_ms", "end_to_end"), ("gpu_kernel_ms", "kernel_only")):
+        hi, lo = first_win(key)
+        if hi is not None and lo is not None:
+            n = lo * 2
+            while n < hi:                                 # x2 refinement between the bracketing sizes
+                measure(n)
+                n *= 2
+            hi, lo = first_win(key)
+        out[f"crossover_bytes_{label}"] = hi
+        out[f"crossover_note_{label}"] = ("GPU faster at every size measured (the crossover lies at or below "
+                                          f"{min(points)} B)" if hi == min(points) else
+                                          "smallest measured size where the GPU is faster")
+    o.close()
+    out["points"] = {str(n): points[n] for n in sorted(points)}
+    out["gpu"] = "pinned H2D + ac_match (sync) + D2H of the matches; median of 50 (10 above 4 MiB), p10/p90"
+    out["cpu"] = f"oracle serial Aho-Corasick match phase, one thread pinned to core {core}, median of 5 (3 above 4 MiB)"
+    out["paper"] = ("paper (Section IV): crossover near 40-50 kB, Intel Core i5-3230M (multifast, serial AC) vs "
+                    "NVIDIA GeForce GT 740M (PFAC), 5 permutation patterns over repeated-alphabet text")
+    log(f"[bench] crossover (1000 keywords): end-to-end {out['crossover_bytes_end_to_end']} B, "
+        f"kernel-only {out['crossover_bytes_kernel_only']} B")
+    return out
+
+
+def bench_dispatch(pf, torch, np, dev, w, a) -> dict:
+    """CPU/GPU dispatch against either unit alone, host text in and host
+    matches out: ac_match_dispatch with the threshold ac_calibrate_dispatch
+    measured, the GPU round trip alone (threshold 0) and the library's CPU
+    matcher alone, over the 1000-keyword workload's sizes."""
+    sample = np.ascontiguousarray(w.text[:16 * MIB])
+    pinned = torch.from_numpy(sample).pin_memory().numpy()
+    thr = a.calibrate_dispatch(pinned)
+    sizes = [KIB, 4 * KIB, 16 * KIB, 64 * KIB, 256 * KIB, MIB, 4 * MIB, 16 * MIB]
+    rows = {}
+    for n in sizes:
+        t = pinned[:n]
+
+        def med(fn, reps=21):
+            ts = []
+            for r in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return round(float(np.median(ts[1:])), 4)
+        a.dispatch_threshold = thr
+        d = med(lambda: a.match_dispatch(t, capacity=n // 64 + 256))
+        a.dispatch_threshold = 0
+        g = med(lambda: a.match_dispatch(t, capacity=n // 64 + 256))
+        c = med(lambda: a.match_host(t, capacity=n // 64 + 256))
+        rows[str(n)] = {"dispatch_ms": d, "gpu_only_ms": g, "cpu_only_ms": c}
+    a.dispatch_threshold = thr
+    log(f"[bench] dispatch: calibrated threshold {thr} B")
+    return {"threshold_bytes": thr, "points": rows,
+            "how": "host text (pinned) in, host matches out; dispatch = ac_match_dispatch with the threshold "
+                   "ac_calibrate_dispatch measured on the first 16 MiB; gpu_only = the same call with threshold 0; "
+                   "cpu_only = ac_match_host (the library's CPU matcher, threads by length); median of 20"}
+
+
+def bench_paper_crossover(pf, torch, np, dev, reps: int = 7) -> dict:
+    """The paper's own experiment (Section IV): permutation patterns over
+    131-byte alphabet lines at k x 16375 B and k x 1310 B, k = 1..41."""
     from oracle import Oracle
     from workloads import paper_workload
+    core = sorted(os.sched_getaffinity(0))[-1]
     out = {"gpu": "pinned H2D + ac_match_ex (sync) + D2H of matches, median of %d" % reps,
-           "cpu": "oracle serial Aho-Corasick match phase, 1 thread, median of %d" % reps}
+           "cpu": "oracle serial Aho-Corasick match phase, one thread pinned to core %d, median of %d" % (core, reps)}
     for n_pat in (5, 10):
         for step_lines, label in ((125, "fig6"), (10, "fig7")):
             w = paper_workload(n_pat, step_lines * 41)
@@ -253,35 +526,19 @@ def bench_crossover(pf, torch, np, dev, reps: int = 7) -> dict:
             sizes, gpu_ms, kern_ms, cpu_ms = [], [], [], []
             for k in range(1, 42):
                 n = 131 * step_lines * k
-                tg, tk, tc = [], [], []
-                for r in range(reps + 1):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    d_text[:n].copy_(host[:n], non_blocking=True)
-                    cnt = a.match_into(d_text[:n], d_off, d_pid, launch=cfg)
-                    h_off[:cnt].copy_(d_off[:cnt], non_blocking=True)
-                    h_pid[:cnt].copy_(d_pid[:cnt], non_blocking=True)
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    tk.append(pf.last_scan_ms())
-                    c0 = time.perf_counter()
-                    eo, _ = o.match(w.text[:n])
-                    c1 = time.perf_counter()
-                    assert len(eo) == cnt
-                    if r:                                   # first round warms up
-                        tg.append((t1 - t0) * 1e3)
-                        tc.append((c1 - c0) * 1e3)
+                g, _, _, kk, cnt = gpu_end_to_end(pf, torch, np, a, host, d_text, d_off, d_pid, h_off, h_pid, n,
+                                                  reps, cfg)
+                c = pinned_oracle_ms(o, w.text[:n], reps, core)
                 sizes.append(n)
-                gpu_ms.append(round(float(np.median(tg)), 4))
-                kern_ms.append(round(float(np.median(tk[1:])), 4))
-                cpu_ms.append(round(float(np.median(tc)), 4))
+                gpu_ms.append(round(g, 4))
+                kern_ms.append(round(kk, 4))
+                cpu_ms.append(round(c, 4))
             o.close()
             cross = next((n for n, g, c in zip(sizes, gpu_ms, cpu_ms) if g < c), None)
             key = f"{label}_{n_pat}_patterns"
             out[key] = {"bytes": sizes, "gpu_end_to_end_ms": gpu_ms, "gpu_kernel_ms": kern_ms,
                         "cpu_ms": cpu_ms, "crossover_bytes": cross}
-            log(f"[bench] crossover {key}: GPU end-to-end beats the CPU from {cross} bytes "
-                f"(GPU {gpu_ms[0]:.3f}..{gpu_ms[-1]:.3f} ms, CPU {cpu_ms[0]:.3f}..{cpu_ms[-1]:.3f} ms)")
+            log(f"[bench] paper crossover {key}: GPU end-to-end beats the CPU from {cross} bytes")
     return out
 
 
@@ -292,15 +549,28 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sweep_1g", choices=["sweep_1g", "large_1g", "tiny", "batched", "served", "crossover"])
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched (and served) figures added to the single-text line")
+                    help="skip the extra figures (large_1g, batched, served, crossover, dispatch) of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mib", type=int, default=256)
+    ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-core", type=int, default=-1, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        if args.cpu_core >= 0:
+            os.sched_setaffinity(0, {args.cpu_core})
+        cpu_baseline_child(args.workload, args.cpu_sample_mib, args.cpu_reps)
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; run with --gpus 1"}))
         log("bench.py: only --gpus 1 is supported (the matcher's multi-GPU sharding is a design, not a run)")
         return 2
+
+    # the CPU baseline runs first, pinned, before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and args.workload in ("sweep_1g", "large_1g", "tiny") and not args.copy_calibration:
+        cpu = cpu_baseline(args.workload, args.cpu_sample_mib, args.cpu_reps)
 
     import numpy as np
     import torch
@@ -332,7 +602,7 @@ def main() -> int:
         return 0
 
     if args.workload == "crossover":
-        b = bench_crossover(pf, torch, np, dev)
+        b = bench_paper_crossover(pf, torch, np, dev)
         print(json.dumps({"metric": "text size from which the GPU beats the serial CPU matcher (paper workload)",
                           "value": b["fig6_5_patterns"]["crossover_bytes"], "unit": "bytes", "n_gpus": 1,
                           "higher_is_better": False, "dtype": "u8", "data": "synthetic",
@@ -351,61 +621,9 @@ def main() -> int:
             "served_x4_rate": b4}), flush=True)
         return 0
 
-    t = time.time()
-    w, desc = make_workload(args.workload)
-    n = len(w.text)
-    log(f"[bench] workload {args.workload}: {n} bytes, {len(w.keywords)} keywords, gen {time.time() - t:.1f}s")
-
-    a = pf.Automaton(w.keywords)
-    info = a.info()
-    launch = a.default_launch(n)
-    log(f"[bench] automaton: {info['n_states']} states, {info['n_classes']} classes, "
-        f"build {info['build_ms']:.1f} ms, launch {launch}")
-
-    host = torch.from_numpy(w.text)
-    # two device copies, each larger than the 256 MB last-level cache, used in turn
-    bufs = [host.to(dev), host.to(dev)]
-    count = a.count(bufs[0])
-    cap = max(1, count)
-    d_off = torch.empty(cap, dtype=torch.int64, device=dev)
-    d_pid = torch.empty(cap, dtype=torch.int32, device=dev)
-    timed_cfg = pf.launch_config(flags=pf.AC_LAUNCH_TIME_SCAN)
-
-    def step(i):
-        got = a.match_into(bufs[i % 2], d_off, d_pid)
-        assert got == count
-
-    def timed_step(i):
-        got = a.match_into(bufs[i % 2], d_off, d_pid, launch=timed_cfg)
-        assert got == count
-        return (pf.last_scan_ms(),) + pf.last_scan_split()
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_per_step * 1e-3) / 1e9
-    # Kernel durations: the same steps again with HIP events taken from the
-    # kernels' own dispatch packets.  They run after the timed region because
-    # reading the events back costs the host ~35 us per call.
-    times = [timed_step(i) for i in range(args.steps)]
-    torch.cuda.synchronize()
-    scan_ms, stream_ms = (float(np.mean([t[i] for t in times])) for i in range(2))
-    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, scan kernel {scan_ms:.3f} ms, {count} matches")
-
-    # roofline of the dominant kernel: the filtered policy's one kernel reads
-    # the text once and writes the matches (12 B each); its hit records are
-    # internal scratch, not algorithmic traffic
-    filtered = launch["policy"] == 1
-    kernel_ms = stream_ms if filtered else scan_ms
-    alg_bytes = n + 12 * count
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload)
+    main_res, w, a, bufs, host = bench_single(pf, torch, np, dev, args.workload, args.steps, args.warmup)
+    n = main_res["text_bytes"]
+    roof = main_res["roofline"]
 
     # achievable read bandwidth of the same buffers (streaming-read probe)
     sink = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -419,6 +637,8 @@ def main() -> int:
         ev1.synchronize()
         probe_ms.append(ev0.elapsed_time(ev1))
     probe_gbps = span / (float(np.median(probe_ms[2:])) * 1e-3) / 1e9
+    roof["achievable_read_gbps"] = round(probe_gbps, 1)
+    roof["frac_of_achievable"] = round(roof["achieved"] / probe_gbps, 4)
 
     # host -> device copy of the text from pinned memory (PCIe-inclusive context)
     pinned = host.pin_memory()
@@ -427,66 +647,50 @@ def main() -> int:
     ev1.record()
     ev1.synchronize()
     h2d_ms = ev0.elapsed_time(ev1)
+    ms_per_step = main_res["ms_per_step"]
 
     result = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": main_res["gbps"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": ms_per_step,
+        "step_ms_p10_p50_p90": main_res["step_ms_p10_p50_p90"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {desc}", "text_bytes": n,
-                   "keywords": len(w.keywords), "matches": count,
-                   "states": info["n_states"], "classes": info["n_classes"],
-                   "launch": launch, "parallelism": "1 GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "kernel": "filtered_kernel" if filtered else "direct_kernel",
-                     "kernel_ms": round(kernel_ms, 4),
-                     "kernel_timing": f"HIP events from the kernels' dispatch packets, mean of {args.steps} "
-                                      "steps run right after the timed region",
-                     "all_kernels_ms": round(scan_ms, 4),
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "achievable_read_gbps": round(probe_gbps, 1),
-                     "frac_of_achievable": round(achieved / probe_gbps, 4)},
-        "breakdown": {"build_ms": round(info["build_ms"], 2),
+        "config": {"workload": main_res["workload"], "text_bytes": n,
+                   "keywords": main_res["keywords"], "matches": main_res["matches"],
+                   "states": main_res["states"], "classes": main_res["classes"],
+                   "launch": main_res["launch"], "parallelism": "1 GPU"},
+        "roofline": roof,
+        "breakdown": {"build_ms": main_res["build_ms"],
                       "h2d_pinned_ms": round(h2d_ms, 3),
                       "h2d_pinned_gbps": round(n / (h2d_ms * 1e-3) / 1e9, 2),
-                      "step_overhead_ms": round(ms_per_step - scan_ms, 4),
+                      "step_overhead_ms": round(ms_per_step - roof["kernel_ms"], 4),
                       "end_to_end_with_h2d_gbps": round(n / ((h2d_ms + ms_per_step) * 1e-3) / 1e9, 2)},
     }
 
     if not args.no_extra and args.workload == "sweep_1g":
-        del bufs, host, pinned
+        result["crossover"] = bench_crossover_sweep(pf, torch, np, dev, w, a)
+        result["dispatch"] = bench_dispatch(pf, torch, np, dev, w, a)
+        del bufs, host, pinned, w, a
+        torch.cuda.empty_cache()
+        lg, _, la, lbufs, lhost = bench_single(pf, torch, np, dev, "large_1g", max(5, args.steps // 2), args.warmup)
+        result["large_1g"] = lg
+        del la, lbufs, lhost
         torch.cuda.empty_cache()
         result["batched"] = bench_batched(pf, torch, np, dev, args.steps, args.warmup)
         torch.cuda.empty_cache()
         result["served"] = bench_served(pf, torch, np, dev)
         result["served_x4_rate"] = bench_served(pf, torch, np, dev, rate_scale=4.0)
 
-    if not args.no_cpu_baseline:
-        from oracle import Oracle
-        sample = min(n, args.cpu_sample_mib << 20)
-        o = Oracle(w.keywords)
-        tc = time.perf_counter()
-        o.match(w.text[:sample])
-        cpu_s = time.perf_counter() - tc
-        o.close()
-        try:
-            model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
-        except Exception:
-            model = "unknown"
-        result["cpu_baseline"] = {"value": round(sample / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
-                                  "kind": "oracle",
-                                  "sample": f"first {sample >> 20} MiB of the same text, serial Aho-Corasick "
-                                            f"(Goto/Failure/Output), match phase only, {cpu_s:.1f} s on {model}"}
-        log(f"[bench] oracle: {sample >> 20} MiB in {cpu_s:.1f} s")
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result), flush=True)
     return 0
 

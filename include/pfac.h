@@ -289,12 +289,18 @@ int ac_default_launch(const ac_automaton *a, int64_t len, ac_launch *out);
  * filter map, segments per chunk) on d_text[0 .. len) (device; a sample of
  * the texts to come), three runs each, and records the fastest for texts of
  * similar length (the same floor(log4 len)).  Later single-text calls whose
- * launch is NULL or leaves every choice at 0 use it; batches keep the
- * built-in rule.  *out (may be NULL) receives the choice.  Synchronises
- * `stream`; every choice computes the same matches.  Errors: AC_EINVAL
- * (NULL automaton or text, len <= 0), AC_EHIP.
+ * launch is NULL or leaves every choice at 0 use it.  *out (may be NULL)
+ * receives the choice.  Synchronises `stream`; every choice computes the same
+ * matches.  Errors: AC_EINVAL (NULL automaton or text, len <= 0), AC_EHIP.
  */
 int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t stream, ac_launch *out);
+
+/* The same for batches: times every choice on one batch (arguments as in
+ * ac_match_batch) and records the fastest for batches of a similar total
+ * length, which later ac_match_batch / ac_match_batch_async calls with a
+ * NULL or all-zero launch use.  Errors: AC_EINVAL (empty batch), AC_EHIP. */
+int ac_tune_batch(ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets, int32_t n_texts,
+                  int64_t total_bytes, hipStream_t stream, ac_launch *out);
 
 const char *ac_last_error(void);
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
     "ac_plan_hash2", "ac_tune", "ac_match_async_noalloc",
     "ac_match_host", "ac_plan_match_host", "ac_match_dispatch", "ac_set_dispatch_threshold",
-    "ac_dispatch_threshold", "ac_calibrate_dispatch",
+    "ac_dispatch_threshold", "ac_calibrate_dispatch", "ac_tune_batch",
 ]
 AC_RAN_CPU, AC_RAN_GPU = 1, 2
 # every symbol include/pfac_serve.h declares
@@ -131,6 +131,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_set_dispatch_threshold": (ctypes.c_int, [vp, i64]),
         "ac_dispatch_threshold": (i64, [vp]),
         "ac_calibrate_dispatch": (ctypes.c_int, [vp, vp, i64, vp, vp]),
+        "ac_tune_batch": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp]),
         "ac_match_batch": (i64, [vp, vp, vp, i32, i64, vp, vp, vp]),
         "ac_match_batch_async": (ctypes.c_int, [vp, vp, vp, i32, i64, vp, vp, vp, vp]),
         "ac_info": (ctypes.c_int, [vp, vp]),

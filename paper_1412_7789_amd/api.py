@@ -172,6 +172,18 @@ class Automaton:
                                  ctypes.byref(cfg)), "ac_tune")
         return cfg.as_dict()
 
+    def tune_batch(self, texts, text_offsets, total_bytes: Optional[int] = None, stream=None) -> Dict[str, int]:
+        """Time every filtered-policy choice on one packed batch and use the
+        fastest for later batches of similar total length."""
+        _check_text(texts)
+        n_texts = text_offsets.numel() - 1
+        total = texts.numel() if total_bytes is None else total_bytes
+        cfg = L.Launch()
+        L.check(L.load().ac_tune_batch(self._h, ctypes.c_void_p(texts.data_ptr()),
+                                       ctypes.c_void_p(text_offsets.data_ptr()), n_texts, total,
+                                       _stream_ptr(stream), ctypes.byref(cfg)), "ac_tune_batch")
+        return cfg.as_dict()
+
     def default_launch(self, n_bytes: int) -> Dict[str, int]:
         cfg = L.Launch()
         L.check(L.load().ac_default_launch(self._h, n_bytes, ctypes.byref(cfg)), "ac_default_launch")

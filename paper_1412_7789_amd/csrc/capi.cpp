@@ -282,11 +282,12 @@ bool all_auto(const ac_launch *l) {
 ac_launch resolved(const ac_automaton *a, const ScanArgs &S, const ac_launch *launch, bool batch) {
     ac_launch cfg{};
     if (launch) cfg = *launch;
-    if (all_auto(launch) && !batch) {
-        // a choice measured by ac_tune for texts of this length, if any
+    if (all_auto(launch)) {
+        // a choice measured by ac_tune / ac_tune_batch for this length, if any
         std::lock_guard<std::mutex> lk(a->tune_mu);
-        auto it = a->tuned.find(length_bucket(S.n));
-        if (it != a->tuned.end()) {
+        const auto &tuned = batch ? a->tuned_batch : a->tuned;
+        auto it = tuned.find(length_bucket(S.n));
+        if (it != tuned.end()) {
             const int32_t flags = cfg.flags;
             cfg = it->second;
             cfg.flags = flags;
@@ -489,6 +490,71 @@ int64_t gpu_round_trip(const ac_automaton *a, const uint8_t *text, int64_t len, 
     return count;
 }
 
+// Times every choice of the filtered policy (stride, filter map, segments)
+// on S, three runs each (the first warms up), and records the fastest for
+// single texts or batches of S's length bucket.
+int tune(ac_automaton *a, const ScanArgs &S, bool batch, hipStream_t stream, ac_launch *out) {
+    const Plan &P = a->host;
+    std::vector<ac_launch> cands;
+    for (int stride : {1, 2, 4}) {
+        if ((stride == 2 && !P.sampled) || (stride == 4 && !P.sampled4)) continue;
+        for (int filter = AC_FILTER_BYTES17; filter <= AC_FILTER_PAIR20; ++filter)
+            for (int segs : {1, 2, 4}) {
+                ac_launch c{};
+                c.policy = AC_POLICY_FILTERED;
+                c.filter = filter;
+                c.segs = segs;
+                c.stride = stride;
+                cands.push_back(c);
+            }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return hip_fail("hipEventCreate", e);
+    int rc = AC_OK;
+    float best_ms = 1e30f;
+    ac_launch best{};
+    for (const ac_launch &c0 : cands) {
+        ac_launch cfg = c0;
+        resolve_launch(a, S.n, batch, cfg);
+        if (cfg.filter != c0.filter || cfg.stride != c0.stride) continue;   // not available here
+        float ms_sum = 0.0f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+            CountSlot *slot = nullptr;
+            if ((rc = slot_for(a, stream, &slot))) break;
+            KernelTiming T;
+            T.scan0 = e0;
+            T.scan1 = e1;
+            ScanArgs SA = S;
+            SA.done = slot->d + 1;
+            slot->stale = true;                  // the next synchronous call clears the count
+            if ((rc = enqueue(a, SA, cfg, batch, true, slot->d, slot->hs, stream, &T))) break;
+            if ((e = hipStreamSynchronize(stream)) != hipSuccess) { rc = hip_fail("hipStreamSynchronize", e); break; }
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail("hipEventElapsedTime", e); break; }
+            if (rep > 0) ms_sum += ms;
+        }
+        if (rc) break;
+        if (ms_sum < best_ms) {
+            best_ms = ms_sum;
+            best = c0;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(a->tune_mu);
+        (batch ? a->tuned_batch : a->tuned)[length_bucket(S.n)] = best;
+    }
+    if (out) {
+        *out = best;
+        resolve_launch(a, S.n, batch, *out);
+    }
+    return AC_OK;
+}
+
 int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const ac_build_opts *opts,
                  ac_automaton **out) {
     if (!out) return fail(AC_EINVAL, "ac_build: NULL output pointer");
@@ -672,68 +738,15 @@ int ac_tune(ac_automaton *a, const uint8_t *d_text, int64_t len, hipStream_t str
     int rc = check_single(a, d_text, len, nullptr);
     if (rc) return rc;
     if (len <= 0) return fail(AC_EINVAL, "ac_tune: empty sample");
-    const Plan &P = a->host;
-    // candidate choices of the filtered policy
-    std::vector<ac_launch> cands;
-    for (int stride : {1, 2, 4}) {
-        if ((stride == 2 && !P.sampled) || (stride == 4 && !P.sampled4)) continue;
-        for (int filter = AC_FILTER_BYTES17; filter <= AC_FILTER_PAIR20; ++filter)
-            for (int segs : {1, 2, 4}) {
-                ac_launch c{};
-                c.policy = AC_POLICY_FILTERED;
-                c.filter = filter;
-                c.segs = segs;
-                c.stride = stride;
-                cands.push_back(c);
-            }
-    }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e != hipSuccess) return hip_fail("hipEventCreate", e);
-    float best_ms = 1e30f;
-    ac_launch best{};
-    const ScanArgs S = single_args(d_text, len, nullptr);
-    for (const ac_launch &c0 : cands) {
-        ac_launch cfg = c0;
-        resolve_launch(a, len, false, cfg);
-        if (cfg.filter != c0.filter || cfg.stride != c0.stride) continue;   // not available here
-        float ms_sum = 0.0f;
-        bool ok = true;
-        for (int rep = 0; rep < 3 && ok; ++rep) {
-            CountSlot *slot = nullptr;
-            if ((rc = slot_for(a, stream, &slot))) { ok = false; break; }
-            KernelTiming T;
-            T.scan0 = e0;
-            T.scan1 = e1;
-            ScanArgs SA = S;
-            SA.done = slot->d + 1;
-            slot->stale = true;                  // the next synchronous call clears the count
-            rc = enqueue(a, SA, cfg, false, true, slot->d, slot->hs, stream, &T);
-            if (rc) { ok = false; break; }
-            if ((e = hipStreamSynchronize(stream)) != hipSuccess) { rc = hip_fail("hipStreamSynchronize", e); ok = false; break; }
-            float ms = 0.0f;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = hip_fail("hipEventElapsedTime", e); ok = false; break; }
-            if (rep > 0) ms_sum += ms;           // the first run warms up
-        }
-        if (!ok) break;
-        if (ms_sum < best_ms) {
-            best_ms = ms_sum;
-            best = c0;
-        }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    return tune(a, single_args(d_text, len, nullptr), false, stream, out);
+}
+
+int ac_tune_batch(ac_automaton *a, const uint8_t *d_texts, const int64_t *d_text_offsets, int32_t n_texts,
+                  int64_t total_bytes, hipStream_t stream, ac_launch *out) {
+    int rc = check_batch(a, d_texts, d_text_offsets, n_texts, total_bytes, nullptr);
     if (rc) return rc;
-    {
-        std::lock_guard<std::mutex> lk(a->tune_mu);
-        a->tuned[length_bucket(len)] = best;
-    }
-    if (out) {
-        *out = best;
-        resolve_launch(a, len, false, *out);
-    }
-    return AC_OK;
+    if (n_texts <= 0 || total_bytes <= 0) return fail(AC_EINVAL, "ac_tune_batch: empty sample");
+    return tune(a, batch_args(d_texts, d_text_offsets, n_texts, total_bytes, nullptr), true, stream, out);
 }
 
 int64_t ac_match(const ac_automaton *a, const uint8_t *d_text, int64_t len, const ac_matches *matches,

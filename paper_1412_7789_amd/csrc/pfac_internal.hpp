@@ -158,6 +158,7 @@ struct ac_automaton {
     // launch choices measured by ac_tune, by text-length bucket (floor(log4 len))
     mutable std::mutex tune_mu;
     std::map<int, ac_launch> tuned;
+    std::map<int, ac_launch> tuned_batch;  // the same for batches, by total length
     // texts shorter than this go to the CPU matcher in ac_match_dispatch
     std::atomic<int64_t> dispatch_bytes{pfac::kDefaultDispatchBytes};
 };

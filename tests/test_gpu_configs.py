@@ -312,6 +312,25 @@ def test_tune_records_a_choice_and_keeps_results():
     assert_same(run_gpu(a, half), Oracle(w.keywords).match(half), "other length")
 
 
+def test_tune_batch_records_a_choice_and_keeps_results():
+    """ac_tune_batch times every filtered choice on a batch; later default
+    batch calls of a similar total length use it, with the same matches."""
+    w = config_batched()
+    n = 1500
+    end = int(w.offsets[n])
+    texts, offsets = w.texts[:end], w.offsets[:n + 1]
+    a = pf.Automaton(w.keywords)
+    d_texts = torch.from_numpy(texts).cuda()
+    d_offs = torch.from_numpy(offsets).cuda()
+    cfg = a.tune_batch(d_texts, d_offs)
+    say("batch tuned", cfg)
+    assert cfg["policy"] == 1 and cfg["stride"] in (1, 2, 4) and cfg["segs"] in (1, 2, 4)
+    tid, off, pid, per = (x.cpu().numpy() for x in a.match_batch(d_texts, d_offs))
+    et, eo, ep = batch_expected(w.keywords, texts, offsets)
+    assert (batch_key(tid, off, pid) == batch_key(et, eo, ep)).all()
+    assert (per == np.bincount(et, minlength=n)).all()
+
+
 @pytest.mark.parametrize("n_texts", [5000, 20000])
 def test_batch_of_one_byte_texts_closed_form(n_texts):
     """Texts of one repeated byte with keywords c^1, c^3, c^7: text i of
