@@ -9,12 +9,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ac_oracle.c")
-LIB = os.path.join(HERE, "libacoracle.so")
+# ORACLE_LIBRARY points the tests at another build (the sanitized one)
+LIB = os.environ.get("ORACLE_LIBRARY") or os.path.join(HERE, "libacoracle.so")
 
 
-def build(src: str = SRC, out: str = LIB, extra=()) -> str:
+def build(src: str = SRC, out: str = LIB, extra=(), cc: str = "gcc") -> str:
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
+    cmd = [cc, "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra",
            *extra, src, "-o", tmp]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)

@@ -6,7 +6,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpfac.so")
+# PFAC_LIBRARY points the binding at another build (the sanitized one)
+LIB_PATH = os.environ.get("PFAC_LIBRARY") or os.path.join(HERE, "libpfac.so")
 
 AC_OK, AC_EINVAL, AC_ENOMEM, AC_EHIP, AC_ENOTSUP = 0, -1, -2, -3, -4
 AC_POLICY_AUTO, AC_POLICY_FILTERED, AC_POLICY_DIRECT = 0, 1, 2
@@ -105,12 +106,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
-    try:
-        # torch's HIP runtime must be the one loaded: the library then shares
-        # it (and its device context) instead of loading a second copy
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    if not os.environ.get("PFAC_NO_TORCH"):
+        try:
+            # torch's HIP runtime must be the one loaded: the library then shares
+            # it (and its device context) instead of loading a second copy
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     if not os.path.exists(path):
         raise ImportError(
             f"{path} is missing: build the HIP library first "

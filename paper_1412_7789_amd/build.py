@@ -30,14 +30,24 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(out: str = LIB, verbose: bool = False) -> str:
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the CPU test
+# leg: every flag reaches the host compiler only, the device code is built as
+# usual, and the runtime is linked as a shared library (preloaded by the test).
+SANITIZE_HOST_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                       "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SANITIZE_LINK_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                       "-Xarch_host", "-shared-libasan"]
+
+
+def build(out: str = LIB, verbose: bool = False, sanitize: bool = False, objdir: str = "") -> str:
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    objdir = os.path.join(HERE, "_build")
+    objdir = objdir or os.path.join(HERE, "_build_sanitize" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
+    extra = SANITIZE_HOST_FLAGS if sanitize else []
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-x", "hip", "-c",
+        cmd = [hipcc, *HIPCC_FLAGS, *extra, f"-I{INCLUDE}", f"-I{CSRC}", "-x", "hip", "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
@@ -55,7 +65,8 @@ def build(out: str = LIB, verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = out + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *(SANITIZE_LINK_FLAGS if sanitize else []),
+           *objs, "-o", tmp, "-lpthread"]
     subprocess.run(cmd, check=True, capture_output=not verbose)
     os.replace(tmp, out)
     return out
