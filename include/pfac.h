@@ -128,7 +128,9 @@ typedef struct {
 #define AC_LAUNCH_TIME_SCAN 1
 
 /*
- * Match every occurrence in d_text[0 .. len) (device).  Writes up to
+ * The scan (Section II's problem; the parallel "N" side of Fig. 3, one walk of
+ * the Fig. 5 trie per offset): every occurrence in d_text[0 .. len) (device).
+ * Writes up to
  * matches->capacity (offset, pattern_id) pairs in unspecified order and
  * returns the TRUE number of matches |R| (>= 0), also when it exceeds the
  * capacity; then an unspecified subset of `capacity` matches is written and
@@ -139,9 +141,11 @@ typedef struct {
  * after every match is written (the kernel may still be retiring; work
  * enqueued later on `stream` runs after it).  The direct policy synchronises
  * the stream instead.  The library keeps per-(device, stream) scratch (a
- * count word and the filtered policy's hit regions), allocated on the
- * stream's first call and grown when a longer text needs more; calls on one
- * stream must come from one thread at a time.  Errors: AC_EINVAL (NULL
+ * count word, a pinned host word and the filtered policy's hit regions,
+ * 16 KiB for each wave of the widest launch the device allows: 64 MiB on a
+ * 256-CU MI355X), allocated on the stream's first call and kept, unchanged,
+ * until ac_release_stream or the end of the process; calls on one stream
+ * must come from one thread at a time.  Errors: AC_EINVAL (NULL
  * automaton, NULL text with len > 0, len < 0, capacity < 0, NULL arrays with
  * capacity > 0), AC_ENOMEM, AC_EHIP.
  */
@@ -155,9 +159,9 @@ int64_t ac_match_ex(const ac_automaton *a, const uint8_t *d_text, int64_t len,
 /*
  * Asynchronous form: enqueues the scan on `stream` and writes the match count
  * to d_count (device int64) without synchronising; returns AC_OK or an error.
- * It clears d_count with a kernel (no memset).  Once the stream's scratch has
- * been sized by an earlier call on a text at least as long, it allocates
- * nothing, so it may then be captured in a HIP graph; replays of captured
+ * It clears d_count with a kernel (no memset).  Only the first call on a
+ * stream allocates (the stream's scratch, sized for any text); after one
+ * call on the stream it may be captured in a HIP graph.  Replays of captured
  * scans that share a stream's scratch must not overlap.
  */
 int ac_match_async(const ac_automaton *a, const uint8_t *d_text, int64_t len,
@@ -195,12 +199,16 @@ typedef struct {
 } ac_batch_matches;
 
 /*
- * Match n_texts texts packed back to back: text t is
+ * The scan of ac_match over many texts at once (each text is its own
+ * instance of Section II's problem): n_texts texts packed back to back, text t is
  * d_texts[d_text_offsets[t] - d_text_offsets[0] .. d_text_offsets[t+1] - d_text_offsets[0])
  * where d_text_offsets (device int64[n_texts + 1], non-decreasing) is read by
  * the kernel.  A match never spans two texts.  One launch scans the whole
- * batch.  Returns the true total count as ac_match does; per_text_count, if
- * given, receives exact per-text counts (it is cleared by the call).
+ * batch.  total_bytes must equal d_text_offsets[n_texts] - d_text_offsets[0]
+ * (the host sizes the launch from it without reading device memory); launch
+ * may be NULL (defaults, or the choice ac_tune_batch recorded).  Returns the
+ * true total count as ac_match does; per_text_count, if given, receives exact
+ * per-text counts (it is cleared by the call).
  * Errors: AC_EINVAL, AC_ENOTSUP (launch->policy == AC_POLICY_DIRECT), AC_EHIP.
  */
 int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts,
@@ -314,6 +322,16 @@ float ac_last_scan_ms(void);
  * or the direct kernel), *walk_ms = time in separate walk kernels (0: the
  * walks run inside the scan kernel); both negative if no timed call was made. */
 void ac_last_scan_split(float *stream_ms, float *walk_ms);
+
+/*
+ * Frees the scratch the library keeps for `stream` on the current device
+ * (count words, the pinned host word, hit regions and ac_match_dispatch's
+ * staging), for a caller about to destroy the stream.  The stream must be
+ * idle (no scan of this library still queued on it) and no other thread may
+ * be calling the library on it.  A later call on the stream allocates the
+ * scratch again.  Returns AC_OK (also when the stream had none) or AC_EHIP.
+ */
+int ac_release_stream(hipStream_t stream);
 
 /* ---- measurement probe -------------------------------------------------------- */
 /*

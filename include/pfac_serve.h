@@ -16,11 +16,13 @@
  *
  * Admission: every request is charged its text bytes plus its match buffer
  * (16 bytes per reserved match) against hbm_budget_bytes, after the
- * registered automata's device bytes.  The oldest waiting request is always
- * served first (no overtaking across automata); when its charge does not fit
- * the budget left by the batches in flight it waits ("admission wait").  The
- * budget is an accounting limit on what is in flight: the server's own
- * device buffers grow to the largest batch seen and are kept.
+ * registered automata's device bytes and the server's own device buffers
+ * (per stream: the scan's scratch and text and match buffers sized for
+ * max_batch_bytes; they grow, and are charged more, if a single request is
+ * larger; ac_server_stats.resident_bytes reports them).  The oldest waiting
+ * request is always served first (no overtaking across automata); when its
+ * charge does not fit the budget left by the batches in flight it waits
+ * ("admission wait").
  *
  * Threads: the server owns one engine thread that makes every HIP call of
  * the server (streams of default priority, created on the device current at
@@ -114,9 +116,11 @@ typedef struct {
     int64_t text_bytes;        /* bytes scanned                                     */
     int64_t admission_waits;   /* times the oldest request waited for budget        */
     int64_t rescans;           /* batches scanned again for lack of match slots     */
-    int64_t peak_charged;      /* largest budget charge in flight (bytes)           */
+    int64_t peak_charged;      /* largest budget charge: automata + resident +
+                                  requests in flight (bytes)                        */
     int64_t max_batch_requests;
-    int64_t reserved[4];
+    int64_t resident_bytes;    /* device bytes of the server's own buffers          */
+    int64_t reserved[3];
 } ac_server_stats;
 
 int ac_server_get_stats(const ac_server *s, ac_server_stats *out);

@@ -26,7 +26,7 @@ EXPORTS = [
     "ac_plan_free", "ac_last_scan_ms", "ac_last_scan_split", "ac_probe_read", "ac_plan_prefix_buckets",
     "ac_plan_hash2", "ac_tune", "ac_match_async_noalloc",
     "ac_match_host", "ac_plan_match_host", "ac_match_dispatch", "ac_set_dispatch_threshold",
-    "ac_dispatch_threshold", "ac_calibrate_dispatch", "ac_tune_batch",
+    "ac_dispatch_threshold", "ac_calibrate_dispatch", "ac_tune_batch", "ac_release_stream",
 ]
 AC_RAN_CPU, AC_RAN_GPU = 1, 2
 # every symbol include/pfac_serve.h declares
@@ -92,7 +92,8 @@ class RequestResult(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("requests", ctypes.c_int64), ("batches", ctypes.c_int64), ("text_bytes", ctypes.c_int64),
                 ("admission_waits", ctypes.c_int64), ("rescans", ctypes.c_int64), ("peak_charged", ctypes.c_int64),
-                ("max_batch_requests", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+                ("max_batch_requests", ctypes.c_int64), ("resident_bytes", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 3)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -150,6 +151,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ac_last_scan_ms": (ctypes.c_float, []),
         "ac_last_scan_split": (None, [vp, vp]),
         "ac_probe_read": (ctypes.c_int, [vp, i64, vp, vp]),
+        "ac_release_stream": (ctypes.c_int, [vp]),
         "ac_server_create": (ctypes.c_int, [vp, vp]),
         "ac_server_destroy": (None, [vp]),
         "ac_server_add_automaton": (ctypes.c_int, [vp, vp]),

@@ -60,6 +60,11 @@ def probe_read(buf, out, stream=None) -> None:
                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "ac_probe_read")
 
 
+def release_stream(stream=None) -> None:
+    """Free the library's scratch for ``stream`` (idle) before it is destroyed."""
+    L.check(L.load().ac_release_stream(_stream_ptr(stream)), "ac_release_stream")
+
+
 def _opts(dense_budget_bytes: int, hash_multiplier: int) -> L.BuildOpts:
     o = L.BuildOpts()
     o.dense_budget_bytes = dense_budget_bytes

@@ -582,7 +582,7 @@ int build_common(const uint8_t *bytes, const int64_t *offsets, int32_t n, const 
 
 int pfac::report_error(int code, const std::string &msg) { return fail(code, msg); }
 
-int pfac::reserve_stream_scratch(hipStream_t stream) {
+int pfac::reserve_stream_scratch(hipStream_t stream, int64_t *device_bytes) {
     int dev = 0, cus = 1;
     int64_t lds_block = 0, lds_cu = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -590,7 +590,10 @@ int pfac::reserve_stream_scratch(hipStream_t stream) {
     int rc = device_props(dev, &cus, &lds_block, &lds_cu);
     if (rc) return rc;
     CountSlot *slot = nullptr;
-    return count_slot(dev, stream, &slot, widest_scan_regions(cus, lds_cu));
+    rc = count_slot(dev, stream, &slot, widest_scan_regions(cus, lds_cu));
+    if (!rc && device_bytes)
+        *device_bytes = 2 * int64_t(sizeof(unsigned long long)) + slot->hs.regions * slot->hs.cap * int64_t(sizeof(uint4));
+    return rc;
 }
 
 void pfac::release_stream_scratch(hipStream_t stream) {
@@ -669,6 +672,14 @@ float ac_last_scan_ms(void) { return g_scan_ms; }
 void ac_last_scan_split(float *stream_ms, float *walk_ms) {
     if (stream_ms) *stream_ms = g_stream_ms;
     if (walk_ms) *walk_ms = g_walk_ms;
+}
+
+int ac_release_stream(hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    pfac::release_stream_scratch(stream);
+    return AC_OK;
 }
 
 int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t stream) {

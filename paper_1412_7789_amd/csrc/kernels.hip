@@ -163,14 +163,17 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
     if (batch) cfg.policy = AC_POLICY_FILTERED;
     if (cfg.policy == AC_POLICY_FILTERED) {
         // Sampling stride and map, chosen by the number of keys the map must
-        // hold.  A stride of 2 halves the probes but holds two windows per
-        // keyword and makes two candidates per positive; the dual map spends a
+        // hold.  A stride of s divides the probes by s but holds s windows per
+        // keyword and makes s candidates per positive; the dual map spends a
         // second hash and LDS read per probe to square the false-positive
-        // rate.  Measured on MI355X (ms per GiB): 1000 printable keywords
-        // (2000 windows) 0.26 with one 2^20-bit map at stride 2, 0.30 dual,
-        // 0.32 at stride 1; 20000 byte keywords (28000 windows) 0.31 dual at
-        // stride 2, 0.44 one map at stride 1, 0.48 dual at stride 1, 0.56 one
-        // map at stride 2.  Stride 4 is used only when asked for.
+        // rate, and the 4-byte-window map (stride 4) sets two bits of one word
+        // per key, which cuts false positives without a second LDS read.
+        // Measured on MI355X (ms per GiB, best segment count): 1000 printable
+        // keywords 0.213 with the 4-byte-window map at stride 4, 0.225 with
+        // one 2^20-bit map at stride 2, 0.229 dual at stride 4, 0.250 dual at
+        // stride 2; 20000 byte keywords (28630 windows at stride 2) 0.269
+        // dual at stride 2, 0.427 with the 4-byte-window map at stride 4,
+        // 0.376 dual at stride 4, 0.558 one map at stride 2.
         const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20;
         const bool auto_stride = cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4;
         const bool small_text = len < (int64_t(16) << 20);

@@ -208,8 +208,9 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
 int report_error(int code, const std::string &msg);
 
 // Creates the (current device, stream) scratch now, so that later scans on
-// the stream allocate nothing.
-int reserve_stream_scratch(hipStream_t stream);
+// the stream allocate nothing; *device_bytes (if given) receives its device
+// memory in bytes.
+int reserve_stream_scratch(hipStream_t stream, int64_t *device_bytes = nullptr);
 // Frees the (current device, stream) scratch; the stream must be idle and is
 // about to be destroyed.
 void release_stream_scratch(hipStream_t stream);

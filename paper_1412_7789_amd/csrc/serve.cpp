@@ -115,6 +115,7 @@ struct Slot {
     int32_t *d_pid = nullptr, *h_pid = nullptr;
     int64_t match_cap = 0;
     int64_t *d_count = nullptr, *h_count = nullptr;
+    int64_t scratch_bytes = 0;      // the scan's per-stream scratch
     // batch in flight
     int phase = 0;                  // 0 idle, 1 scan + counts, 2 matches coming back
     std::vector<ReqPtr> batch;
@@ -162,6 +163,11 @@ int grow(Slot &s, int64_t text_bytes, int64_t texts, int64_t matches) {
     return AC_OK;
 }
 
+// Device memory a slot holds: its buffers and the scan's stream scratch.
+int64_t slot_device_bytes(const Slot &s) {
+    return s.text_cap + (s.texts_cap + 1) * 8 + s.texts_cap * 8 + s.match_cap * (4 + 8 + 4) + 8 + s.scratch_bytes;
+}
+
 void release_slot(Slot &s) {
     for (void *p : {static_cast<void *>(s.d_text), static_cast<void *>(s.d_offs), static_cast<void *>(s.d_per),
                     static_cast<void *>(s.d_tid), static_cast<void *>(s.d_off), static_cast<void *>(s.d_pid),
@@ -186,6 +192,9 @@ struct ac_server {
     int device = 0;
     std::vector<const ac_automaton *> auts;
     int64_t aut_bytes = 0;
+    // device bytes of the server's own buffers (all slots), charged against
+    // the budget like the automata; written by the engine thread under mu
+    int64_t resident = 0;
 
     mutable std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -201,11 +210,21 @@ struct ac_server {
     std::thread engine;
 
     void run();
+    void note_resident();
     bool launch(Slot &s, std::vector<ReqPtr> batch);
     bool advance(Slot &s);
     void finish(Slot &s, int status);
     int enqueue_scan(Slot &s);
 };
+
+// Recomputes the resident bytes after a slot's buffers grew.
+void ac_server::note_resident() {
+    int64_t r = 0;
+    for (const auto &sl : slots) r += slot_device_bytes(sl);
+    std::lock_guard<std::mutex> lk(mu);
+    resident = r;
+    stats.resident_bytes = r;
+}
 
 int ac_server::enqueue_scan(Slot &s) {
     ac_batch_matches m{s.d_tid, s.d_off, s.d_pid, s.cap, s.d_per};
@@ -233,7 +252,9 @@ bool ac_server::launch(Slot &s, std::vector<ReqPtr> batch) {
         s.charged += r->charge;
     }
     const int64_t n = int64_t(s.batch.size());
+    const int64_t before = slot_device_bytes(s);
     int rc = grow(s, s.total, n, s.cap);
+    if (slot_device_bytes(s) != before) note_resident();
     hipError_t e = hipSuccess;
     if (!rc) {
         int64_t pos = 0;
@@ -267,7 +288,9 @@ bool ac_server::advance(Slot &s) {
         const int64_t count = *s.h_count;
         if (count > s.cap) {
             // more matches than reserved slots: scan the resident texts again
+            const int64_t before = slot_device_bytes(s);
             int rc = grow(s, s.total, int64_t(s.batch.size()), count);
+            if (slot_device_bytes(s) != before) note_resident();
             s.cap = count;
             if (!rc) rc = enqueue_scan(s);
             if (rc) { finish(s, rc); return true; }
@@ -365,7 +388,7 @@ void ac_server::run() {
                     aut_ids[size_t(i)] = waiting[size_t(i)]->aut;
                     lens[size_t(i)] = waiting[size_t(i)]->len;
                 }
-                const int64_t free_budget = o.budget - aut_bytes - inflight_charge;
+                const int64_t free_budget = o.budget - aut_bytes - resident - inflight_charge;
                 const int32_t k = plan_batch(o, n, aut_ids.data(), lens.data(), free_budget, picked.data());
                 if (k == 0) {
                     if (!blocked) stats.admission_waits++;
@@ -381,7 +404,7 @@ void ac_server::run() {
                 int64_t c = 0;
                 for (const auto &r : batch) c += r->charge;
                 inflight_charge += c;
-                stats.peak_charged = std::max(stats.peak_charged, inflight_charge + aut_bytes);
+                stats.peak_charged = std::max(stats.peak_charged, inflight_charge + aut_bytes + resident);
             }
             launch(s, std::move(batch));
             progressed = true;
@@ -438,11 +461,17 @@ int ac_server_create(const ac_server_opts *opts, ac_server **out) {
         }
         if ((rc = dev_alloc(&sl.d_count, 1)) || (rc = host_alloc(&sl.h_count, 1))) break;
         // the scan's scratch: hit regions for the widest launch
-        if ((rc = pfac::reserve_stream_scratch(sl.stream))) break;
+        if ((rc = pfac::reserve_stream_scratch(sl.stream, &sl.scratch_bytes))) break;
         // sized for a full batch, so that serving never reallocates (a single
         // request longer than max_batch_bytes still grows its stream's buffers)
         const int64_t texts = std::min<int64_t>(o.max_batch_texts, 1 << 16);
         rc = grow(sl, o.max_batch_bytes, texts, reserve_matches(o, o.max_batch_bytes) + 256 * texts);
+    }
+    if (!rc) {
+        s->note_resident();
+        if (s->resident > o.budget)
+            rc = report_error(AC_EINVAL, "ac_server_create: the server's own buffers (" + std::to_string(s->resident) +
+                                             " bytes) exceed the HBM budget");
     }
     if (rc) {
         for (auto &sl : s->slots) release_slot(sl);
@@ -470,7 +499,7 @@ int ac_server_add_automaton(ac_server *s, const ac_automaton *a) {
     if (!s || !a) return report_error(AC_EINVAL, "ac_server_add_automaton: NULL argument");
     if (a->device != s->device) return report_error(AC_EINVAL, "ac_server_add_automaton: automaton on another device");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->aut_bytes + a->dbytes > s->o.budget)
+    if (s->aut_bytes + s->resident + a->dbytes > s->o.budget)
         return report_error(AC_EINVAL, "ac_server_add_automaton: automata exceed the HBM budget");
     s->auts.push_back(a);
     s->aut_bytes += a->dbytes;
@@ -491,7 +520,7 @@ int64_t ac_server_submit(ac_server *s, int32_t automaton, const uint8_t *text, i
             return report_error(AC_EINVAL, "ac_server_submit: unknown automaton id");
         r->a = s->auts[size_t(automaton)];
         if (s->stop) return report_error(AC_EINVAL, "ac_server_submit: server is stopping");
-        if (r->charge > s->o.budget - s->aut_bytes)
+        if (r->charge > s->o.budget - s->aut_bytes - s->resident)
             return report_error(AC_EINVAL, "ac_server_submit: request larger than the HBM budget");
         r->id = s->next_id++;
         r->submit_ns = now_ns();

@@ -360,6 +360,32 @@ def test_concurrent_host_threads_on_their_own_streams():
     assert not errors, errors[0]
 
 
+def test_released_stream_scratch_is_rebuilt():
+    """ac_release_stream frees a stream's scratch; the next call on the stream
+    allocates it again and gives the same result.  Releasing a stream the
+    library never used, or twice, is harmless."""
+    w = config_tiny()
+    a = pf.Automaton(w.keywords)
+    text = w.text[:(1 << 19) + 13]
+    exp = oracle_match(w.keywords, text)
+    s = torch.cuda.Stream()
+    pf.release_stream(s)
+    with torch.cuda.stream(s):
+        d = torch.from_numpy(text).cuda()
+        for r in range(3):
+            off, pid = a.match(d, stream=s)
+            assert_same((off.cpu().numpy(), pid.cpu().numpy()), exp, f"call {r}")
+            s.synchronize()
+            pf.release_stream(s)
+            pf.release_stream(s)
+        assert a.count(d, stream=s) == len(exp[0])
+        off, pid, ran = a.match_dispatch(text, stream=s)
+        assert ran == pf.AC_RAN_GPU
+        assert_same((off, pid), exp, "dispatch after release")
+    s.synchronize()
+    pf.release_stream(s)
+
+
 def test_every_offset_matches_closed_form():
     """A text of one repeated byte with keywords c^L: every offset is a
     candidate and a hit, walks run 32 states deep past keywords ending on the

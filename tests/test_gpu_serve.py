@@ -66,6 +66,12 @@ def served():
     return w, automata, alone, exp
 
 
+def resident_of(**opts):
+    """Device bytes of a server's own buffers (charged against its budget)."""
+    with pf.Server(pf.server_opts(**opts)) as probe:
+        return probe.stats()["resident_bytes"]
+
+
 def run_burst(w, automata, opts, texts=None, which=None):
     texts = texts_of(w) if texts is None else texts
     which = w.automaton if which is None else which
@@ -107,11 +113,20 @@ def test_fifo_mode_equals_oracle(served):
 def test_small_budget_forces_admission_waits(served):
     w, automata, alone, exp = served
     aut_bytes = sum(a.info()["device_bytes"] for a in automata)
-    opts = pf.server_opts(hbm_budget_bytes=aut_bytes + 3 * pf.serve_charge(2 * MIB), n_streams=4)
+    resident = resident_of(n_streams=4)
+    # per stream at least the scan's scratch and a full batch's text buffer
+    assert resident >= 4 * (256 << 20)
+    with pytest.raises(pf.PfacError):
+        pf.Server(pf.server_opts(hbm_budget_bytes=resident - 1, n_streams=4))
+    with pf.Server(pf.server_opts(hbm_budget_bytes=resident + 1024, n_streams=4)) as srv:
+        with pytest.raises(pf.PfacError):
+            srv.add_automaton(automata[0])
+    opts = pf.server_opts(hbm_budget_bytes=aut_bytes + resident + 3 * pf.serve_charge(2 * MIB), n_streams=4)
     res, st = run_burst(w, automata, opts)
     say("small budget stats", st)
     assert st["admission_waits"] > 0
-    assert st["peak_charged"] <= opts.hbm_budget_bytes
+    assert st["resident_bytes"] == resident
+    assert aut_bytes + resident < st["peak_charged"] <= opts.hbm_budget_bytes
     for i, (off, pid, meta) in enumerate(res):
         assert_same((off, pid), exp[i], f"request {i} vs oracle")
 
@@ -183,7 +198,8 @@ def test_replay_reports_latencies(served):
 
 def test_submit_errors():
     a = pf.Automaton([b"abc"])
-    with pf.Server(pf.server_opts(hbm_budget_bytes=a.info()["device_bytes"] + pf.serve_charge(4096))) as srv:
+    budget = resident_of() + a.info()["device_bytes"] + pf.serve_charge(4096)
+    with pf.Server(pf.server_opts(hbm_budget_bytes=budget)) as srv:
         assert srv.add_automaton(a) == 0
         with pytest.raises(pf.PfacError):
             srv.submit(1, np.zeros(10, np.uint8))            # unknown automaton
