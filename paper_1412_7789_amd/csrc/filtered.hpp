@@ -15,7 +15,12 @@ namespace pfac {
 namespace dev {
 
 
-constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
+constexpr int kQueueCap = 256;
+// Hit records a wave keeps in LDS before it spills further ones to its
+// global region.  Global stores in the streaming loop stall it (a later wait
+// for the next chunk's loads also waits for them, and the data registers a
+// store reads cannot be reused until it is done), so records stay on chip.
+constexpr int kLdsHits = 64;   // per-wave candidate queue (entries)
 constexpr int kDrain = 64;       // candidates taken per drain (1 per lane; 128 and 192 measured slower)
 // A queue holds fewer than kDrain entries before a push round and gains at
 // most one per lane in it, so its last entries are never used by the queue:
@@ -532,6 +537,16 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
     return (static_cast<unsigned long long>(hi) << 32) | lo;
 }
 
+// A condition every lane of the wave agrees on, marked as such for the
+// compiler, so that branching on it needs no exec-mask bookkeeping.
+__device__ __forceinline__ bool uniform(bool c) { return __builtin_amdgcn_readfirstlane(int(c)) != 0; }
+// A value every lane holds, moved to scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 // The kernel's argument block, read where it lies.  The empty asm hides the
 // pointer's origin from the compiler, so the fields read through it are
 // loaded here and not all at the kernel's entry, from where they would stay
@@ -582,8 +597,13 @@ template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL, bool P
 __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
     __shared__ __align__(16) uint8_t sfilt[1 << FLOG2];
     __shared__ __align__(16) uint32_t squeue[kMaxWaves * kQueueCap];
-    constexpr int PT_SLOTS = FLOG2 >= 17 ? 2048 : 8192;   // prefix-table slots that fit beside the filter
-    __shared__ __align__(16) uint32_t sptab[2 * PT_SLOTS];
+    // Beside a 64 KiB filter, a copy of the prefix table (8192 slots) fits
+    // too; beside a 128 KiB one only the queues and the hit records do.
+    constexpr int PT_SLOTS = FLOG2 >= 17 ? 0 : 8192;
+    constexpr int kHitBytes = kMaxWaves * kLdsHits * 16;
+    __shared__ __align__(16) uint32_t sxtra[(2 * PT_SLOTS * 4 + kHitBytes) / 4];
+    uint32_t *const sptab = sxtra;                                        // [2 * PT_SLOTS]
+    uint4 *const shits = reinterpret_cast<uint4 *>(sxtra + 2 * PT_SLOTS);  // [waves * kLdsHits]
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
     constexpr int PER_LANE = kDrain / kWave;
     const int waves_per_block = int(blockDim.x) / kWave;
@@ -628,7 +648,8 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
 
     // Where the streaming loop stopped: every slot from `cur` on is left to
     // the slow mode (none if cur_ok is false), cur's candidates not yet
-    // queued in `rest`, and lane 0's `ahead` holding the slot after nxt.
+    // queued in `rest`, and lane 0's `ahead` holding the slot after nxt
+    // (taken when nxt is a chunk of the text).
     bool slow = false;
     bool cur_ok = false;
     uint32_t cur = 0, nxt = 0, ahead = 0;
@@ -642,17 +663,23 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         const uint32_t *gptab = P1->A.ptab;
         const int ptab_bits = P1->A.ptab_bits;
         const uint32_t mul = P1->A.hash_mul;
-        const bool pt_lds = ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
-        if (pt_lds) {
-            const uint4 *src = reinterpret_cast<const uint4 *>(gptab);
-            uint4 *dst = reinterpret_cast<uint4 *>(sptab);
-            for (int i = threadIdx.x; i < (2 << ptab_bits) / 4; i += blockDim.x) dst[i] = src[i];
-        }
-        {
-            const uint4 *src = reinterpret_cast<const uint4 *>(F.filter);
-            uint4 *dst = reinterpret_cast<uint4 *>(sfilt);
-            for (int i = threadIdx.x; i < (1 << FLOG2) / 16; i += blockDim.x) dst[i] = src[i];
-        }
+        const bool pt_lds = FLOG2 < 17 && ptab_bits <= 13;
+        // Tables to LDS, two loads in flight per thread.  Every block reads
+        // the same lines, so the blocks of one XCD (blockIdx mod 8) start at
+        // different ones (n16 is a power of two).
+        auto stage = [&](const uint4 *src, uint4 *dst, int n16) __attribute__((always_inline)) {
+            const int rot = (int(blockIdx.x >> 3) * 1024) & (n16 - 1);
+            for (int i0 = int(threadIdx.x); i0 < n16; i0 += 2 * int(blockDim.x)) {
+                const int i1 = i0 + int(blockDim.x);
+                const uint4 v0 = src[(i0 + rot) & (n16 - 1)];
+                uint4 v1;
+                if (i1 < n16) v1 = src[(i1 + rot) & (n16 - 1)];
+                dst[(i0 + rot) & (n16 - 1)] = v0;
+                if (i1 < n16) dst[(i1 + rot) & (n16 - 1)] = v1;
+            }
+        };
+        stage(reinterpret_cast<const uint4 *>(F.filter), reinterpret_cast<uint4 *>(sfilt), (1 << FLOG2) / 16);
+        if (pt_lds) stage(reinterpret_cast<const uint4 *>(gptab), reinterpret_cast<uint4 *>(sptab), (2 << ptab_bits) / 4);
         SlotMap M;
         M.bfirst = F.c_lo + int64_t(blockIdx.x) * waves_per_block;
         M.nw = nw;
@@ -662,12 +689,13 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         __syncthreads();
 
         uint4 *hits = F.hits + w * F.hit_cap;
+        uint4 *lhits = shits + wave * kLdsHits;
         // Streaming-loop drain of the newest `take` entries (interior chunks
         // only: there o + 16 <= n, so the aligned 16 bytes from (o & ~3) lie
         // in the text and give the prefix and the 8 bytes after it).  Refuses
         // when the region might not hold its hits.
         auto drain_store = [&](int take) __attribute__((always_inline)) {
-            if (hcount + kDrain > F.hit_cap) return false;
+            if (hcount + kDrain > kLdsHits + F.hit_cap) return false;
             uint32_t ent[PER_LANE];
             pop(take, ent);
             u32x4 win[PER_LANE];
@@ -701,7 +729,11 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
                 }
                 const unsigned long long hit = __ballot(e != 0u);
                 if (hit == 0) continue;
-                if (e != 0u) gstore16(hits + hcount + int(rank_in(hit)), ent[r], e, rb0, rb1);
+                if (e != 0u) {
+                    const int at = hcount + int(rank_in(hit));
+                    if (at < kLdsHits) lhits[at] = make_uint4(ent[r], e, rb0, rb1);
+                    else gstore16(hits + (at - kLdsHits), ent[r], e, rb0, rb1);
+                }
                 hcount += __popcll(hit);
             }
             return true;
@@ -713,31 +745,33 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         // chunk): with a fixed number of loads between a chunk's loads and
         // its first use, the compiler waits for that chunk only.
         ChunkRegs<SEGS> ra, rb;
+        const int64_t c_hi = uniform64(F.c_hi);
         cur = uint32_t(wave);
         nxt = uint32_t(wave + waves_per_block);
-        if (lane == 0) ahead = atomicAdd(&snext, 1u);
-        cur_ok = M.chunk(cur) < F.c_hi;
+        cur_ok = uniform(M.chunk(cur) < c_hi);
         if (cur_ok) load_interior<SEGS>(F, M.chunk(cur), lane, ra);
-        auto advance = [&]() __attribute__((always_inline)) {
+        // One half step: issue the next chunk's loads into `into` (or reload
+        // the current one), take the slot after nxt from the block's counter
+        // (lane 0), filter and queue the current chunk held in `regs`, then
+        // move on.  The counter's divergent branch joins right after the
+        // atomic, so the loop's back edge merges only uniform conditions.
+        // Returns false when the loop must end (slow mode, or no slot left).
+        auto half = [&](ChunkRegs<SEGS> &regs, ChunkRegs<SEGS> &into) __attribute__((always_inline)) {
+            const bool nxt_ok = uniform(M.chunk(nxt) < c_hi);
+            load_interior<SEGS>(F, M.chunk(nxt_ok ? nxt : cur), lane, into);
+            if (lane == 0 && nxt_ok) ahead = atomicAdd(&snext, 1u);
+            rest = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(regs, lane, sfilt, mul);
+            if (!uniform(push(rest, cur, drain_store))) { slow = true; return false; }
             // slots held by a wave only grow, and so do their chunks: once
             // one is past the end, so is every later one
             cur = nxt;
-            cur_ok = M.chunk(cur) < F.c_hi;
+            cur_ok = nxt_ok;
             nxt = __builtin_amdgcn_readfirstlane(ahead);
-            if (lane == 0 && cur_ok) ahead = atomicAdd(&snext, 1u);
+            return cur_ok;
         };
         while (cur_ok) {
-            const bool nxt_ok = M.chunk(nxt) < F.c_hi;
-            load_interior<SEGS>(F, M.chunk(nxt_ok ? nxt : cur), lane, rb);
-            rest = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(ra, lane, sfilt, mul);
-            if (!push(rest, cur, drain_store)) { slow = true; break; }
-            advance();
-            if (!cur_ok) break;
-            const bool nxt_ok2 = M.chunk(nxt) < F.c_hi;
-            load_interior<SEGS>(F, M.chunk(nxt_ok2 ? nxt : cur), lane, ra);
-            rest = filter_chunk<K, BITMAP, SEGS, FLOG2, STRIDE, DUAL, PAIR>(rb, lane, sfilt, mul);
-            if (!push(rest, cur, drain_store)) { slow = true; break; }
-            advance();
+            if (!half(ra, rb)) break;
+            if (!half(rb, ra)) break;
         }
         while (!slow && qlen > 0)
             if (!drain_store(imin(qlen, kDrain))) slow = true;
@@ -753,7 +787,7 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
     M.nw = nw;
     M.wmask = uint32_t(waves_per_block - 1);
     M.wlog = wlog;
-    const bool pt_lds = A.ptab_bits <= (FLOG2 >= 17 ? 11 : 13);
+    const bool pt_lds = FLOG2 < 17 && A.ptab_bits <= 13;
     const uint32_t mul = A.hash_mul;
     uint4 *hits = F.hits + w * F.hit_cap;
     auto offset_of = [&](uint32_t ent) __attribute__((always_inline)) {
@@ -838,7 +872,13 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         wave_sync();
         for (int i = int(lane); i < hcount; i += kWave) {
-            const u32x4 rec = gload16(reinterpret_cast<const uint8_t *>(hits + i));
+            uint4 rec;
+            if (i < kLdsHits) {
+                rec = shits[wave * kLdsHits + i];
+            } else {
+                const u32x4 g = gload16(reinterpret_cast<const uint8_t *>(hits + (i - kLdsHits)));
+                rec = make_uint4(g.x, g.y, g.z, g.w);
+            }
             const int64_t o = offset_of(rec.x);
             auto put = [&](int32_t pid) __attribute__((always_inline)) {
                 const uint32_t at = atomicAdd(&q[0], 1u);
@@ -921,7 +961,8 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         for (int32_t i = int32_t(threadIdx.x); i < total; i += int32_t(blockDim.x)) {
             int j = 0;
             while (wfirst[j + 1] <= i) ++j;          // wave (region) of flat index i
-            const uint4 rec = F.hits[(r0 + j) * F.hit_cap + (i - wfirst[j])];
+            const int k = i - wfirst[j];
+            const uint4 rec = k < kLdsHits ? shits[j * kLdsHits + k] : F.hits[(r0 + j) * F.hit_cap + (k - kLdsHits)];
             const int64_t o = offset_of(rec.x);
             int64_t tstart, end;
             int32_t tid;

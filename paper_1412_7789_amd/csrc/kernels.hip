@@ -108,8 +108,8 @@ FilteredFn pick_filtered(int K, int kind, int segs, int stride) {
 }
 
 int64_t filtered_lds(const FilterGeom &g) {
-    const int64_t pt_slots = g.bytes > (64 << 10) ? 2048 : 8192;
-    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + pt_slots * 8;
+    const int64_t pt_slots = g.bytes > (64 << 10) ? 0 : 8192;
+    return g.bytes + int64_t(kMaxWaves) * kQueueCap * 4 + pt_slots * 8 + int64_t(kMaxWaves) * kLdsHits * 16;
 }
 
 // Launch geometry of the filtered policy for a text of n bytes at `addr`.
@@ -211,15 +211,11 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         if (cfg.block != 256 && cfg.block != 512 && cfg.block != 1024) cfg.block = 1024;
         // Texts under 32 MiB take one segment per wave step, which spreads
         // them over more waves (measured on MI355X: a 1 MiB scan in 11 us
-        // instead of 19 with four segments).  Above that, the dual map takes
-        // four segments and the others two (1 GiB on MI355X: 1000 keywords,
-        // 4-byte-window map at stride 4, 0.213 ms at two and 0.219 at four;
-        // 20000 keywords, dual map at stride 2, 0.269 ms at four and 0.283
-        // at two).
-        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) {
-            if (len < (int64_t(32) << 20)) cfg.segs = 1;
-            else cfg.segs = g.dual ? 4 : 2;
-        }
+        // instead of 19 with four segments).  Above that, two (1 GiB on
+        // MI355X: 1000 keywords, 4-byte-window map at stride 4, 0.213 ms at
+        // two and 0.219 at four; the dual map's four-segment kernel spills
+        // registers).
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = len < (int64_t(32) << 20) ? 1 : 2;
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
     } else {
