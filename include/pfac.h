@@ -96,11 +96,11 @@ typedef struct {
 #define AC_FILTER_BITS19    4  /* 2^19-bit map, 64 KiB of LDS                   */
 #define AC_FILTER_DUAL19    5  /* two 2^19-bit maps with independent hashes,   */
                                /* 128 KiB of LDS; both bits must be set         */
-#define AC_FILTER_PAIR20    6  /* stride 4 only: a 2^20-bit map (128 KiB of LDS) */
-                               /* keyed by the keywords' 4-byte windows at      */
-                               /* positions 1 .. 4, two bits per key in one     */
-                               /* word: both must be set; needs every keyword   */
-                               /* >= 8 bytes                                    */
+#define AC_FILTER_PAIR20    6  /* strides 2 and 4: a 2^20-bit map (128 KiB of   */
+                               /* LDS) keyed by the keywords' 4-byte windows at */
+                               /* positions 1 .. stride, two bits per key in    */
+                               /* one word: both must be set; needs every       */
+                               /* keyword >= stride + 4 bytes                   */
 
 typedef struct {
     int32_t policy;         /* AC_POLICY_*                                        */
@@ -282,8 +282,9 @@ typedef struct {
     int64_t prefix_table_bytes;  /* exact prefix -> state table                 */
     int64_t tail_bytes;      /* forced-path leaves + keyword bytes               */
     int32_t n_windows4;      /* distinct 3-byte windows at positions 1 .. 4 (0 = stride 4 unavailable) */
-    int32_t n_quads4;        /* distinct 4-byte windows at positions 1 .. 4 (0 = AC_FILTER_PAIR20 unavailable) */
-    int32_t reserved[2];
+    int32_t n_quads4;        /* distinct 4-byte windows at positions 1 .. 4 (0 = no stride-4 AC_FILTER_PAIR20) */
+    int32_t n_quads2;        /* distinct 4-byte windows at positions 1 and 2 (0 = no stride-2 AC_FILTER_PAIR20) */
+    int32_t reserved[1];
 } ac_info_t;
 
 int ac_info(const ac_automaton *a, ac_info_t *out);
@@ -373,7 +374,7 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                              with hash h owns bit h mod 32 of word (or byte)
  *                              h >> shift; the stride-2 and stride-4 maps also
  *                              set it at index (h + 31) >> shift.
- *                              AC_FILTER_PAIR20 (stride 4 only): the 4-byte
+ *                              AC_FILTER_PAIR20 (strides 2 and 4): the 4-byte
  *                              window x owns bits h mod 32 and (x >> 24) mod 32
  *                              of word h >> 17, h = ac_plan_hash(x)
  */

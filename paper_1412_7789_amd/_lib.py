@@ -71,7 +71,8 @@ class Info(ctypes.Structure):
                 ("output_bytes", ctypes.c_int64), ("filter_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("build_ms", ctypes.c_double),
                 ("prefix_table_bytes", ctypes.c_int64), ("tail_bytes", ctypes.c_int64),
-                ("n_windows4", ctypes.c_int32), ("n_quads4", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("n_windows4", ctypes.c_int32), ("n_quads4", ctypes.c_int32), ("n_quads2", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}

@@ -231,6 +231,7 @@ void fill_info(const Plan &P, ac_info_t *o) {
     o->n_windows2 = P.sampled ? P.n_windows2 : 0;
     o->n_windows4 = P.sampled4 ? P.n_windows4 : 0;
     o->n_quads4 = P.pair4 ? P.n_quads4 : 0;
+    o->n_quads2 = P.pair2 ? P.n_quads2 : 0;
     o->dense_bytes = int64_t(P.dense.size()) * 4;
     o->compact_bytes = int64_t(P.node.size()) * 4 + int64_t(P.label.size());
     o->output_bytes = int64_t(P.out_off.size() + P.out_pid.size()) * 4;

@@ -14,22 +14,23 @@
 namespace pfac {
 namespace dev {
 
-
-constexpr int kQueueCap = 256;
+constexpr int kQueueCap = 256;   // per-wave candidate queue (entries)
 // Hit records a wave keeps in LDS before it spills further ones to its
 // global region.  Global stores in the streaming loop stall it (a later wait
 // for the next chunk's loads also waits for them, and the data registers a
 // store reads cannot be reused until it is done), so records stay on chip.
-constexpr int kLdsHits = 64;   // per-wave candidate queue (entries)
+constexpr int kLdsHits = 64;
 constexpr int kDrain = 64;       // candidates taken per drain (1 per lane; 128 and 192 measured slower)
 // A queue holds fewer than kDrain entries before a push round and gains at
 // most one per lane in it, so its last entries are never used by the queue:
 // the last dword of the first wave's queue holds the block's slot counter.
 static_assert(2 * kDrain <= kQueueCap - 4, "queue room");
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
-// AC_FILTER_PAIR20 is the default (for texts of 16 MiB and more) up to this
-// many 4-byte windows: two bits per key fill about 2 keys / 2^15 of the map
+// AC_FILTER_PAIR20 is the default (for texts of 16 MiB and more) at stride 4
+// up to this many 4-byte windows, else at stride 2 up to kPair2MaxKeys: two
+// bits per key fill about 2 keys / 2^15 of the map
 constexpr int32_t kPairMaxKeys = 12000;
+constexpr int32_t kPair2MaxKeys = 32768;
 // (queue entry, keyword id) pairs a wave's queue holds as its match stage,
 // after its count and before the slot counter
 constexpr int kWaveStageCap = (kQueueCap - 4) / 2;
@@ -455,10 +456,10 @@ __device__ __forceinline__ void load_partial(const FilterLaunch &F, int64_t c, u
 // rotating the word right by p (mod 32) moves the key's bit (x * mul) mod 32
 // to b.  Adding c may carry into the word index; the host sets each key's
 // bit in both words that can result.
-// PAIR (stride 4): the window at s is the whole register d[s / 4], four
-// bytes, tested against the keywords' 4-byte windows at positions 1 .. 4:
-// its first three bytes pick the word, and the bits (x * mul) mod 32 and
-// (byte 3) mod 32 of that word must both be set.
+// PAIR (strides 2 and 4): the window at s is four bytes (the whole register
+// d[s / 4] when s is a multiple of 4), tested against the keywords' 4-byte
+// windows at positions 1 .. STRIDE: its first three bytes pick the word, and
+// the bits (x * mul) mod 32 and (byte 3) mod 32 of that word must both be set.
 template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL, bool PAIR>
 __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
                                                            const uint8_t *sfilt, uint32_t mul) {
@@ -1015,8 +1016,8 @@ FilteredFn pick_filter(int kind, int segs) {
         case AC_FILTER_BYTES16: return pick_segs<K, false, 16, STRIDE>(segs);
         case AC_FILTER_DUAL19: return pick_segs<K, true, 17, STRIDE, true>(segs);
         case AC_FILTER_PAIR20:
-            // stride 4 only (resolve_launch never pairs it with another stride)
-            if constexpr (STRIDE == 4) return pick_segs<K, true, 17, STRIDE, false, true>(segs);
+            // strides 2 and 4 only (resolve_launch never pairs it with stride 1)
+            if constexpr (STRIDE == 2 || STRIDE == 4) return pick_segs<K, true, 17, STRIDE, false, true>(segs);
             else return nullptr;
         default: return pick_segs<K, true, 16, STRIDE>(segs);
     }

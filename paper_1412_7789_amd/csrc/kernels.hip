@@ -168,12 +168,13 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         // second hash and LDS read per probe to square the false-positive
         // rate, and the 4-byte-window map (stride 4) sets two bits of one word
         // per key, which cuts false positives without a second LDS read.
-        // Measured on MI355X (ms per GiB, best segment count): 1000 printable
-        // keywords 0.213 with the 4-byte-window map at stride 4, 0.225 with
-        // one 2^20-bit map at stride 2, 0.229 dual at stride 4, 0.250 dual at
-        // stride 2; 20000 byte keywords (28630 windows at stride 2) 0.269
-        // dual at stride 2, 0.427 with the 4-byte-window map at stride 4,
-        // 0.376 dual at stride 4, 0.558 one map at stride 2.
+        // Measured on MI355X (ms per GiB, two segments): 1000 printable
+        // keywords 0.193 with the 4-byte-window map at stride 4, 0.214 with
+        // it at stride 2, 0.217 with one 2^20-bit map at stride 2, 0.269
+        // dual at stride 2; 20000 byte keywords (29958 4-byte windows at
+        // stride 2) 0.275 with the 4-byte-window map at stride 2, 0.284 dual
+        // at stride 2, 0.437 with the 4-byte-window map at stride 4, 0.567
+        // with one 2^20-bit map at stride 2.
         const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20;
         const bool auto_stride = cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4;
         const bool small_text = len < (int64_t(16) << 20);
@@ -183,6 +184,7 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
                 cfg.filter = AC_FILTER_PAIR20;
             } else if (P.sampled && P.n_windows2 <= 65536) {
                 cfg.stride = 2;
+                if (auto_filter && !small_text && P.pair2 && P.n_quads2 <= kPair2MaxKeys) cfg.filter = AC_FILTER_PAIR20;
             } else {
                 cfg.stride = 1;
             }
@@ -190,7 +192,8 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         if (cfg.stride == 4 && !P.sampled4) cfg.stride = P.sampled ? 2 : 1;
         if (cfg.stride == 2 && !P.sampled) cfg.stride = 1;
         // the 4-byte-window map exists at stride 4 only
-        if (cfg.filter == AC_FILTER_PAIR20 && (cfg.stride != 4 || !P.pair4)) cfg.filter = AC_FILTER_AUTO;
+        if (cfg.filter == AC_FILTER_PAIR20 && !((cfg.stride == 4 && P.pair4) || (cfg.stride == 2 && P.pair2)))
+            cfg.filter = AC_FILTER_AUTO;
         if (cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20) {
             // keys in the filter: prefixes (stride 1) or windows (strides 2, 4)
             const int64_t keys = cfg.stride == 4 ? P.n_windows4 : cfg.stride == 2 ? P.n_windows2 : P.n_prefixes;

@@ -55,9 +55,9 @@ constexpr uint32_t kFilterMul2 = 0x7FEB35u;       // hash of the second map of A
 // the keywords' K-byte prefixes; stride 2 tests the windows starting at every
 // second offset against the 3-byte windows at keyword positions 1 and 2
 // (built when K = 3 and every keyword has >= 5 bytes); stride 4 every fourth
-// one against positions 1 .. 4 (keywords of >= 7 bytes), and its
-// AC_FILTER_PAIR20 map holds the 4-byte windows there (keywords of >= 8
-// bytes).  A set's AC_FILTER_PAIR20 slot is empty at strides 1 and 2.
+// one against positions 1 .. 4 (keywords of >= 7 bytes).  The
+// AC_FILTER_PAIR20 map of strides 2 and 4 holds the 4-byte windows at those
+// positions instead (keywords of >= 6 and >= 8 bytes); it is empty at stride 1.
 constexpr int kNumFilters = 3 * kNumFilterKinds;   // strides 1, 2 and 4
 // Filter set of a sampling stride: 0 (stride 1), 1 (stride 2), 2 (stride 4).
 constexpr int stride_set(int stride) { return stride == 4 ? 2 : stride - 1; }
@@ -86,6 +86,8 @@ struct Plan {
     bool sampled4 = false;         // the stride-4 filters exist
     int32_t n_quads4 = 0;          // distinct 4-byte windows at keyword positions 1 .. 4
     bool pair4 = false;            // the stride-4 AC_FILTER_PAIR20 map exists
+    int32_t n_quads2 = 0;          // distinct 4-byte windows at keyword positions 1 and 2
+    bool pair2 = false;            // the stride-2 AC_FILTER_PAIR20 map exists
     std::vector<uint8_t> filter[kNumFilters];   // indexed by stride_set(stride) * kNumFilterKinds + kind - 1
     int32_t ptab_bits = 0;
     std::vector<uint32_t> ptab;    // [2 << ptab_bits]: buckets of 4 {key, value} slots

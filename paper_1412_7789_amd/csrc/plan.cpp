@@ -281,20 +281,25 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
     const std::vector<uint32_t> windows4 = P.sampled4 ? windows_of(4) : std::vector<uint32_t>();
     P.n_windows2 = int32_t(windows.size());
     P.n_windows4 = int32_t(windows4.size());
-    // 4-byte windows at positions 1 .. 4 (keywords of 8 bytes or more)
-    P.pair4 = P.K == 3 && P.min_len >= 8;
-    std::vector<uint32_t> quads4;
-    if (P.pair4) {
-        quads4.reserve(size_t(n) * 4);
+    // 4-byte windows at positions 1 .. count (keywords of count + 4 bytes or more)
+    auto quads_of = [&](int count) {
+        std::vector<uint32_t> w;
+        w.reserve(size_t(n) * size_t(count));
         for (int32_t p = 0; p < n; ++p) {
             const uint8_t *k = kw(p);
-            for (int j = 1; j <= 4; ++j)
-                quads4.push_back(uint32_t(k[j]) | uint32_t(k[j + 1]) << 8 | uint32_t(k[j + 2]) << 16 |
-                                 uint32_t(k[j + 3]) << 24);
+            for (int j = 1; j <= count; ++j)
+                w.push_back(uint32_t(k[j]) | uint32_t(k[j + 1]) << 8 | uint32_t(k[j + 2]) << 16 |
+                            uint32_t(k[j + 3]) << 24);
         }
-        std::sort(quads4.begin(), quads4.end());
-        quads4.erase(std::unique(quads4.begin(), quads4.end()), quads4.end());
-    }
+        std::sort(w.begin(), w.end());
+        w.erase(std::unique(w.begin(), w.end()), w.end());
+        return w;
+    };
+    P.pair2 = P.K == 3 && P.min_len >= 6;
+    P.pair4 = P.K == 3 && P.min_len >= 8;
+    const std::vector<uint32_t> quads2 = P.pair2 ? quads_of(2) : std::vector<uint32_t>();
+    const std::vector<uint32_t> quads4 = P.pair4 ? quads_of(4) : std::vector<uint32_t>();
+    P.n_quads2 = int32_t(quads2.size());
     P.n_quads4 = int32_t(quads4.size());
     // A key x with hash h = x * mul (mod 2^32) owns bit h mod 32 of word (or
     // byte) h >> shift.  The sampled kernels hash x * mul + c with 0 <= c <
@@ -310,9 +315,10 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             if (g.pair) {
                 // 4-byte window x: bits h mod 32 and (x >> 24) mod 32 of word h >> shift,
                 // h the hash of its first three bytes (the kernel adds nothing to h)
-                if (set != 2 || !P.pair4) { f.clear(); continue; }
+                const bool have = (set == 1 && P.pair2) || (set == 2 && P.pair4);
+                if (!have) { f.clear(); continue; }
                 f.assign(size_t(g.bytes), 0);
-                for (uint32_t x : quads4) {
+                for (uint32_t x : set == 1 ? quads2 : quads4) {
                     const uint32_t h = prefix_hash(x & 0xFFFFFFu, mul);
                     const size_t w = size_t(h >> g.shift) * 4;
                     for (uint32_t bit : {h & 31u, (x >> 24) & 31u}) f[w + bit / 8] |= uint8_t(1u << (bit % 8));

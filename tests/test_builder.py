@@ -285,9 +285,9 @@ def test_rotated_bit_test_finds_every_key():
 
 
 def test_pair_map_holds_both_bits_of_every_4_byte_window():
-    """AC_FILTER_PAIR20 (stride 4): every 4-byte window x at keyword
-    positions 1 .. 4 owns bits h mod 32 and (x >> 24) mod 32 of word h >> 17,
-    h the hash of its first three bytes; the map exists only at stride 4."""
+    """AC_FILTER_PAIR20 (strides 2 and 4): every 4-byte window x at keyword
+    positions 1 .. stride owns bits h mod 32 and (x >> 24) mod 32 of word
+    h >> 17, h the hash of its first three bytes; no such map at stride 1."""
     kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
     T = Tables(kws)
     quads = {k[j:j + 4] for k in kws for j in (1, 2, 3, 4)}
@@ -301,11 +301,24 @@ def test_pair_map_holds_both_bits_of_every_4_byte_window():
         assert (w >> (h & 31)) & 1 and (w >> ((x >> 24) & 31)) & 1
     # bits set: at most two per window
     assert sum(bin(int(v)).count("1") for v in words) <= 2 * len(quads)
-    for set_ in (0, 1):
-        assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + 6 * set_ + L.AC_FILTER_PAIR20, np.uint8)) == 0
-    # keywords shorter than 8 bytes: no 4-byte-window map
+    # stride 2: the 4-byte windows at positions 1 and 2, the same layout
+    quads2 = {k[j:j + 4] for k in kws for j in (1, 2)}
+    assert T.info["n_quads2"] == len(quads2)
+    words2 = T.plan.export(L.AC_TABLE_FILTER_BASE + 6 + L.AC_FILTER_PAIR20, np.uint8).view(np.uint32)
+    assert len(words2) == 1 << 15
+    for q in quads2:
+        x = int.from_bytes(q, "little")
+        h = T.plan.hash(x & 0xFFFFFF)
+        w = int(words2[h >> 17])
+        assert (w >> (h & 31)) & 1 and (w >> ((x >> 24) & 31)) & 1
+    assert sum(bin(int(v)).count("1") for v in words2) <= 2 * len(quads2)
+    assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + L.AC_FILTER_PAIR20, np.uint8)) == 0
+    # keywords shorter than 8 bytes: no stride-4 map; shorter than 6: no stride-2 map
     T7 = Tables([b"abcdefg", b"bcdefghij"])
-    assert T7.info["n_quads4"] == 0 and T7.info["n_windows4"] > 0
+    assert T7.info["n_quads4"] == 0 and T7.info["n_windows4"] > 0 and T7.info["n_quads2"] > 0
+    T5 = Tables([b"abcde", b"bcdefghij"])
+    assert T5.info["n_quads2"] == 0 and T5.info["n_windows2"] > 0
+    assert len(T5.plan.export(L.AC_TABLE_FILTER_BASE + 6 + L.AC_FILTER_PAIR20, np.uint8)) == 0
 
 
 def test_sampled_filters_need_long_enough_keywords():

@@ -97,7 +97,8 @@ def test_sweep_policies_agree():
     exp = Oracle(w.keywords).match(w.text)
     for cfg in [dict(policy=1, filter=f, segs=s, block=b, stride=st) for f in (1, 2, 3, 4, 5) for s in (1, 2, 4)
                 for b in (256, 1024) for st in (1, 2, 4)] + \
-               [dict(policy=1, filter=6, segs=s, block=b, stride=4) for s in (1, 2, 4) for b in (256, 512, 1024)] + \
+               [dict(policy=1, filter=6, segs=s, block=b, stride=st) for s in (1, 2, 4) for b in (256, 512, 1024)
+                for st in (2, 4)] + \
                [dict(policy=2)]:
         say("sweep policy", cfg)
         assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
@@ -134,7 +135,7 @@ def test_large_automaton_64mib_full():
     assert_same(run_gpu(a, w.text), exp, "large 64 MiB")
     for cfg in [dict(policy=1, filter=1, stride=1), dict(policy=1, filter=4, segs=1, stride=2),
                 dict(policy=1, filter=2, stride=2), dict(policy=1, filter=5, stride=1),
-                dict(policy=1, filter=6, stride=4), dict(policy=2)]:
+                dict(policy=1, filter=6, stride=4), dict(policy=1, filter=6, stride=2, segs=2), dict(policy=2)]:
         say("large policy", cfg)
         assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
 

@@ -57,6 +57,8 @@ POLICIES = [
     ("dual19-s4", dict(policy=1, filter=5, segs=4)),
     ("dual19-stride1-s2-b512", dict(policy=1, filter=5, segs=2, stride=1, block=512)),
     ("pair20-falls-back", dict(policy=1, filter=6, segs=4, stride=4)),
+    ("pair20-stride2-s2", dict(policy=1, filter=6, segs=2, stride=2)),
+    ("pair20-stride2-s1-b256", dict(policy=1, filter=6, segs=1, stride=2, block=256)),
     ("direct-lds", dict(policy=2, table_in_lds=1)),
     ("direct-global", dict(policy=2, table_in_lds=2)),
 ]
@@ -183,7 +185,8 @@ def test_hit_region_overflow(stride, filt):
 
 
 @pytest.mark.parametrize("cfg", [None, dict(policy=1, stride=2, filter=2, segs=4),
-                                 dict(policy=1, stride=4, filter=6, segs=2), dict(policy=1, stride=1, segs=1)])
+                                 dict(policy=1, stride=4, filter=6, segs=2), dict(policy=1, stride=2, filter=6, segs=2),
+                                 dict(policy=1, stride=1, segs=1)])
 def test_dense_stretch_sends_some_waves_to_slow_mode(cfg):
     """32 MiB of the 1000-keyword workload with 2 MiB of one repeated byte
     in the middle and two keywords made of that byte: the waves that draw the
