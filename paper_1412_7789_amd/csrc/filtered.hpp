@@ -218,6 +218,10 @@ __device__ __forceinline__ uint2 prefix_state(LoadBucket load, int bits, uint32_
     u32x4 q[4];
     load(b1, q[0], q[1]);
     load(b2, q[2], q[3]);
+    // all four loads go out before the first compare: left alone, the
+    // scheduler started comparing the first bucket first, so the second
+    // bucket's loads waited for the first's (two round trips, not one)
+    __builtin_amdgcn_sched_barrier(0);
     uint2 r = make_uint2(0u, 0u);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -539,8 +543,10 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
 }
 
 // A condition every lane of the wave agrees on, marked as such for the
-// compiler, so that branching on it needs no exec-mask bookkeeping.
-__device__ __forceinline__ bool uniform(bool c) { return __builtin_amdgcn_readfirstlane(int(c)) != 0; }
+// compiler, so that branching on it needs no exec-mask bookkeeping.  The
+// ballot keeps the lane mask in scalar registers (a readfirstlane would first
+// write it to a VGPR, whose reuse could wait for a load still in flight).
+__device__ __forceinline__ bool uniform(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
 // A value every lane holds, moved to scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
