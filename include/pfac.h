@@ -362,10 +362,13 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                                          final 1<<31 (0 = empty slot); a prefix lies in
  *                                          one of the two buckets ac_plan_prefix_buckets gives
  *   AC_TABLE_TAIL       int32[S]           leaf reached by a forced path, or -1
- *   AC_TABLE_TAIL_INFO  int32[4*S]         per state: {leaf, keyword-byte position of the
- *                                          first byte below the state, bytes to the leaf,
- *                                          the leaf's only keyword id + 1 or 0}; first
- *                                          field -2 at a leaf, -1 without a forced path
+ *   AC_TABLE_TAIL_INFO  int32[4*S]         per state, one walk step's record: {leaf,
+ *                                          keyword-byte position of the first byte below
+ *                                          the state, bytes to the leaf, the leaf's only
+ *                                          keyword id + 1 or 0} for a forced path;
+ *                                          {-2, 0, 0, 0} at a leaf; {-1, first child,
+ *                                          child count, 0} otherwise; bit 31 of the last
+ *                                          field set when a keyword ends at the state
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
  *                              k = 6 + AC_FILTER_* (stride 2, may be empty),
  *                              k = 12 + AC_FILTER_* (stride 4, may be empty);

@@ -326,50 +326,104 @@ __device__ __forceinline__ bool equal_bytes(const uint8_t *t, const uint8_t *k, 
     return d == 0;
 }
 
+// Position of byte b among the first n (1 .. 16) bytes of v, which are
+// distinct, or -1.  Per word, the lowest flag of the zero-byte test marks the
+// first byte equal to b exactly (a false flag can only sit above a true one).
+__device__ __forceinline__ int find_byte16(u32x4 v, int n, uint32_t b) {
+    const uint32_t rep = b * 0x01010101u;
+    int at = 16;
+#pragma unroll
+    for (int i = 3; i >= 0; --i) {
+        const uint32_t x = v[i] ^ rep;
+        const uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;
+        if (z) at = 4 * i + int(__builtin_ctz(z) >> 3);
+    }
+    return at < n ? at : -1;
+}
+
 // The rest of the walk from offset o (relative to the scanned buffer) once
-// the exact prefix table gave e = {state at depth K | final bit}: further
-// transitions come from the transition table, and once the remaining path is
-// forced (a unary chain to a leaf with no keyword ending in between) the
-// leaf's keyword is compared with the text directly.  The walk never reads
-// at or past `end` (the end of o's text).  With REC, rb holds the 8 text
-// bytes that follow the prefix (as captured by the streaming kernel), so most
-// walks end without reading the text again.  Every keyword starting at o is
-// reported, through ids(state) for all keyword ids of a final state or
-// one(pid) for a single id.
+// the exact prefix table gave e = {state at depth K | final bit}.  Each step
+// reads the state's 16-byte walk record (tail info): whether a keyword ends
+// there, and either a forced path (a unary chain to a leaf with no keyword
+// ending in between, whose leaf keyword is then compared with the text
+// directly) or the state's children.  A dense state's next state comes from
+// its transition row, with the byte's class loaded beside the record; a
+// compact state's children are consecutive states with sorted edge labels,
+// found among up to 16 labels read in one load.  The walk never reads at or
+// past `end` (the end of o's text).  With REC, rb holds the 8 text bytes that
+// follow the prefix (as captured by the streaming kernel); the 16 bytes after
+// those (after the prefix without REC) are loaded once at the start, so most
+// walks read no single text bytes.  Every keyword starting at o is reported,
+// through ids(state) for all keyword ids of a final state or one(pid) for a
+// single id.
 template <bool REC, typename Ids, typename One>
 __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, int64_t o, int64_t end, uint32_t e,
                                           uint2 rb, Ids &&ids, One &&one) {
     const int K = A.K;
     if (o + K > end) return;          // the prefix ran into the next text of a batch
+    constexpr int kRec = REC ? 8 : 0;
+    u32x4 more = {0u, 0u, 0u, 0u};    // text bytes o + K + kRec .. + 16
+    if (o + K + kRec < end) {
+        const uint8_t *p = S.text + o + K + kRec;
+        const uintptr_t tend = reinterpret_cast<uintptr_t>(S.text) + uintptr_t(S.n);
+        more = reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p)
+                                                            : load16_clamped(p, (tend - 1u) & ~uintptr_t(3));
+    }
     auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
+        int64_t r = j - o - K;
         if (REC) {
-            const int64_t r = j - o - K;
             if (r < 4) return (rb.x >> (8 * r)) & 0xFFu;
             if (r < 8) return (rb.y >> (8 * (r - 4))) & 0xFFu;
+            r -= 8;
+        }
+        if (r < 16) {
+            const uint32_t w = r < 4 ? more.x : r < 8 ? more.y : r < 12 ? more.z : more.w;
+            return (w >> (8 * (r & 3))) & 0xFFu;
         }
         return gload1(S.text + j);
     };
     int32_t s = int32_t(e & kStateMask);
     int64_t d = K;
-    if (e >> 31) ids(s);
     while (true) {
         const int4 ti = A.tailinfo[s];
+        const bool has_byte = o + d < end;
+        const uint32_t b = has_byte ? byte_at(o + d) : 0u;
+        const bool dense = s < A.S_dense;
+        const uint32_t c = dense && has_byte ? uint32_t(A.cls[b]) : 0u;
+        if (ti.w < 0) ids(s);          // a keyword ends at s
         if (ti.x >= 0) {
             // forced path: bytes d .. d + ti.z of the text against the keyword
             const int64_t L = d + ti.z;
             if (o + L > end) return;
             if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
-            if (ti.w > 0) one(ti.w - 1);
+            const int32_t only = ti.w & 0x7fffffff;
+            if (only > 0) one(only - 1);
             else ids(ti.x);
             return;
         }
-        if (ti.x == -2) return;        // a leaf: nothing below
-        if (o + d >= end) return;
-        const int32_t e2 = step_global(A, A.cls, s, byte_at(o + d));
-        if (e2 == 0) return;
-        s = e2 & 0x7fffffff;
+        if (ti.x == -2 || !has_byte) return;   // a leaf, or the text ends
+        if (dense) {
+            const int32_t e2 = A.dense[static_cast<int64_t>(s) * A.C + c];
+            if (e2 == 0) return;
+            s = e2 & 0x7fffffff;
+        } else {
+            const int32_t fc = ti.y, nc = ti.z;
+            int i;
+            if (nc <= 16) {
+                i = find_byte16(load16_any(A.label + fc), nc, b);
+            } else {
+                int32_t lo = 0, hi = nc;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (A.label[fc + mid] < b) lo = mid + 1;
+                    else hi = mid;
+                }
+                i = lo < nc && A.label[fc + lo] == b ? lo : -1;
+            }
+            if (i < 0) return;
+            s = fc + i;
+        }
         ++d;
-        if (e2 < 0) ids(s);
     }
 }
 

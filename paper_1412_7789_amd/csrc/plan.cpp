@@ -405,21 +405,31 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             else if (!is_final(c)) P.tail[size_t(s)] = P.tail[size_t(c)];
         }
     }
-    // per state: {leaf, position in kw_bytes of the first byte below s, bytes
-    // from s down to the leaf, leaf's only keyword id + 1 or 0} when tail[s]
-    // is a deeper leaf; first field -2 when s is itself a leaf, -1 when the
-    // path below s is not forced
+    // per state, everything one step of a walk needs in one 16-byte record:
+    // {leaf, position in kw_bytes of the first byte below s, bytes from s
+    // down to the leaf, leaf's only keyword id + 1 or 0} when tail[s] is a
+    // deeper leaf; {-2, 0, 0, 0} when s is itself a leaf; {-1, first child,
+    // child count, 0} when the path below s is not forced.  Bit 31 of the
+    // last field is set when a keyword ends at s.
     P.tailinfo.assign(size_t(S) * 4, 0);
     for (int32_t s = 0; s < S; ++s) {
         const int32_t t = P.tail[size_t(s)];
         int32_t *ti = &P.tailinfo[size_t(s) * 4];
-        if (t < 0 || t == s) { ti[0] = t < 0 ? -1 : -2; continue; }
-        const int32_t p = P.out_pid[size_t(P.out_off[size_t(t)])];
-        ti[0] = t;
-        ti[1] = int32_t(offsets[p] - offsets[0]) + P.depth[size_t(s)];
-        ti[2] = P.depth[size_t(t)] - P.depth[size_t(s)];
-        // the leaf's keyword id + 1 when exactly one keyword ends there
-        ti[3] = P.out_off[size_t(t) + 1] - P.out_off[size_t(t)] == 1 ? p + 1 : 0;
+        if (t < 0) {
+            ti[0] = -1;
+            ti[1] = P.first_child[size_t(s)];
+            ti[2] = P.n_child[size_t(s)];
+        } else if (t == s) {
+            ti[0] = -2;
+        } else {
+            const int32_t p = P.out_pid[size_t(P.out_off[size_t(t)])];
+            ti[0] = t;
+            ti[1] = int32_t(offsets[p] - offsets[0]) + P.depth[size_t(s)];
+            ti[2] = P.depth[size_t(t)] - P.depth[size_t(s)];
+            // the leaf's keyword id + 1 when exactly one keyword ends there
+            ti[3] = P.out_off[size_t(t) + 1] - P.out_off[size_t(t)] == 1 ? p + 1 : 0;
+        }
+        if (is_final(s)) ti[3] = int32_t(uint32_t(ti[3]) | kFinalBit);
     }
     // keyword bytes (for tail comparisons) with int32 offsets
     P.kw_bytes.assign(bytes + offsets[0], bytes + offsets[0] + total);

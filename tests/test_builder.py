@@ -209,14 +209,20 @@ def test_prefix_table_and_tails(name, kws):
         leaf = t if (t is not None and not T.children(t)) else None
         assert T.tail[s] == (leaf if leaf is not None else -1), s
         ti = T.tailinfo[s]
+        # bit 31 of the last field: a keyword ends at s
+        assert (int(ti[3]) < 0) == bool(T.outputs(s)), s
+        only = int(ti[3]) & 0x7FFFFFFF
         if leaf is None:
-            assert ti[0] == -1
+            # not forced: the children are states ti[1] .. ti[1] + ti[2] - 1
+            ch = sorted(t for t, _ in T.children(s))
+            assert ti[0] == -1 and ch == list(range(int(ti[1]), int(ti[1]) + int(ti[2]))), s
+            assert only == 0
         elif leaf == s:
-            assert ti[0] == -2
+            assert ti[0] == -2 and ti[1] == 0 and ti[2] == 0 and only == 0
         else:
             assert ti[0] == leaf and ti[2] == len(path) - 1
             ids = T.out_pid[T.out_off[leaf]:T.out_off[leaf + 1]]
-            assert ti[3] == (ids[0] + 1 if len(ids) == 1 else 0)
+            assert only == (ids[0] + 1 if len(ids) == 1 else 0)
             # the keyword bytes at ti[1] spell the path below s
             kw = kws[ids[0]]
             d = int(T.depth[s])
