@@ -99,8 +99,8 @@ typedef struct {
 #define AC_FILTER_PAIR20    6  /* strides 2 and 4: a 2^20-bit map (128 KiB of   */
                                /* LDS) keyed by the keywords' 4-byte windows at */
                                /* positions 1 .. stride, two bits per key in    */
-                               /* one word: both must be set; needs every       */
-                               /* keyword >= stride + 4 bytes                   */
+                               /* one word (three at stride 2): all must be     */
+                               /* set; needs every keyword >= stride + 4 bytes  */
 
 typedef struct {
     int32_t policy;         /* AC_POLICY_*                                        */
@@ -379,7 +379,8 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                              set it at index (h + 31) >> shift.
  *                              AC_FILTER_PAIR20 (strides 2 and 4): the 4-byte
  *                              window x owns bits h mod 32 and (x >> 24) mod 32
- *                              of word h >> 17, h = ac_plan_hash(x)
+ *                              of word h >> 17, h = ac_plan_hash(x), and at
+ *                              stride 2 also bit (x >> 16) mod 32
  */
 #define AC_TABLE_CLASS_MAP  1
 #define AC_TABLE_DENSE      2

@@ -517,7 +517,9 @@ __device__ __forceinline__ void load_partial(const FilterLaunch &F, int64_t c, u
 // PAIR (strides 2 and 4): the window at s is four bytes (the whole register
 // d[s / 4] when s is a multiple of 4), tested against the keywords' 4-byte
 // windows at positions 1 .. STRIDE: its first three bytes pick the word, and
-// the bits (x * mul) mod 32 and (byte 3) mod 32 of that word must both be set.
+// the bits (x * mul) mod 32 and (byte 3) mod 32 of that word must both be set;
+// at stride 2 also bit (byte 2) mod 32, read from the next sampled window
+// (whose low bits are byte 2) at no extra extraction.
 template <int K, bool BITMAP, int SEGS, int FLOG2, int STRIDE, bool DUAL, bool PAIR>
 __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS> &R, unsigned lane,
                                                            const uint8_t *sfilt, uint32_t mul) {
@@ -565,7 +567,14 @@ __device__ __forceinline__ unsigned long long filter_chunk(const ChunkRegs<SEGS>
                 if (PAIR) {
                     const uint32_t p0 = hash24(x, mul);
                     const uint32_t w1 = fm[p0 >> shift];
-                    const uint32_t v = __builtin_amdgcn_alignbit(w1, w1, p0) & __builtin_amdgcn_alignbit(w1, w1, x >> 24);
+                    uint32_t v = __builtin_amdgcn_alignbit(w1, w1, p0) & __builtin_amdgcn_alignbit(w1, w1, x >> 24);
+                    if (STRIDE == 2) {
+                        // third bit: (byte 2) mod 32, the low bits of the next sampled window
+                        const int s2 = s + 2, w2 = s2 >> 2;
+                        const uint32_t x2 = s2 > 16 ? d[4] >> 16
+                                          : (s2 & 3) ? __builtin_amdgcn_alignbyte(d[w2 + 1], d[w2], 2u) : d[w2];
+                        v &= __builtin_amdgcn_alignbit(w1, w1, x2);
+                    }
                     mj |= (v & 1u) << b;
                 } else if (BITMAP) {
                     uint32_t v;

@@ -314,14 +314,16 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             if ((set == 1 && !P.sampled) || (set == 2 && !P.sampled4)) { f.clear(); continue; }
             if (g.pair) {
                 // 4-byte window x: bits h mod 32 and (x >> 24) mod 32 of word h >> shift,
-                // h the hash of its first three bytes (the kernel adds nothing to h)
+                // h the hash of its first three bytes (the kernel adds nothing to h);
+                // the stride-2 map also sets bit (x >> 16) mod 32
                 const bool have = (set == 1 && P.pair2) || (set == 2 && P.pair4);
                 if (!have) { f.clear(); continue; }
                 f.assign(size_t(g.bytes), 0);
                 for (uint32_t x : set == 1 ? quads2 : quads4) {
                     const uint32_t h = prefix_hash(x & 0xFFFFFFu, mul);
                     const size_t w = size_t(h >> g.shift) * 4;
-                    for (uint32_t bit : {h & 31u, (x >> 24) & 31u}) f[w + bit / 8] |= uint8_t(1u << (bit % 8));
+                    const uint32_t third = set == 1 ? (x >> 16) & 31u : h & 31u;
+                    for (uint32_t bit : {h & 31u, (x >> 24) & 31u, third}) f[w + bit / 8] |= uint8_t(1u << (bit % 8));
                 }
                 continue;
             }

@@ -293,7 +293,8 @@ def test_rotated_bit_test_finds_every_key():
 def test_pair_map_holds_both_bits_of_every_4_byte_window():
     """AC_FILTER_PAIR20 (strides 2 and 4): every 4-byte window x at keyword
     positions 1 .. stride owns bits h mod 32 and (x >> 24) mod 32 of word
-    h >> 17, h the hash of its first three bytes; no such map at stride 1."""
+    h >> 17, h the hash of its first three bytes, and at stride 2 also bit
+    (x >> 16) mod 32; no such map at stride 1."""
     kws = make_keywords(SPECS["sweep"], np.random.default_rng(0), np.random.default_rng(1))
     T = Tables(kws)
     quads = {k[j:j + 4] for k in kws for j in (1, 2, 3, 4)}
@@ -316,8 +317,15 @@ def test_pair_map_holds_both_bits_of_every_4_byte_window():
         x = int.from_bytes(q, "little")
         h = T.plan.hash(x & 0xFFFFFF)
         w = int(words2[h >> 17])
-        assert (w >> (h & 31)) & 1 and (w >> ((x >> 24) & 31)) & 1
-    assert sum(bin(int(v)).count("1") for v in words2) <= 2 * len(quads2)
+        assert (w >> (h & 31)) & 1 and (w >> ((x >> 24) & 31)) & 1 and (w >> ((x >> 16) & 31)) & 1
+    assert sum(bin(int(v)).count("1") for v in words2) <= 3 * len(quads2)
+    # and no bit a window does not own: rebuilt from the windows, the map is the same
+    rebuilt = np.zeros(1 << 15, dtype=np.uint32)
+    for q in quads2:
+        x = int.from_bytes(q, "little")
+        h = T.plan.hash(x & 0xFFFFFF)
+        rebuilt[h >> 17] |= np.uint32((1 << (h & 31)) | (1 << ((x >> 24) & 31)) | (1 << ((x >> 16) & 31)))
+    assert np.array_equal(rebuilt, words2)
     assert len(T.plan.export(L.AC_TABLE_FILTER_BASE + L.AC_FILTER_PAIR20, np.uint8)) == 0
     # keywords shorter than 8 bytes: no stride-4 map; shorter than 6: no stride-2 map
     T7 = Tables([b"abcdefg", b"bcdefghij"])
