@@ -287,6 +287,11 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
     def batched(i):
         assert a.match_batch_into(d_texts, d_offs, tid, off, pid, per) == count
     ms_batch = timed(batched, steps)
+
+    # without per-text counts (text ids only): no clearing kernel before the scan
+    def batched_ids(i):
+        assert a.match_batch_into(d_texts, d_offs, tid, off, pid) == count
+    ms_batch_ids = timed(batched_ids, steps)
     launch_default = None
     # graph: capture the asynchronous batch call on a stream of its own
     s = torch.cuda.Stream()
@@ -316,12 +321,15 @@ def bench_batched(pf, torch, np, dev, steps: int, warmup: int) -> dict:
         assert got == count
     ms_plain = timed(plain, max(1, steps // 10))
     gbps = lambda ms: total / (ms * 1e-3) / 1e9
-    log(f"[bench] batched: {ms_batch:.3f} ms/batch ({gbps(ms_batch):.0f} GB/s), graph {ms_graph:.3f} ms, "
+    log(f"[bench] batched: {ms_batch:.3f} ms/batch ({gbps(ms_batch):.0f} GB/s), ids only {ms_batch_ids:.3f} ms, "
+        f"graph {ms_graph:.3f} ms, "
         f"tuned {ms_tuned:.3f} ms {tuned}, per-text calls {ms_plain:.2f} ms ({gbps(ms_plain):.1f} GB/s)")
     return {"workload": f"{n_texts} texts, log-normal lengths (median 8 KiB, sigma 2.1, clipped to 64 B..4 MiB), "
                         "2000 printable keywords |k| 8..32, Poisson plants 1 per 4 KiB; seed 0",
             "texts": n_texts, "bytes": total, "matches": count,
             "batched_gbps": round(gbps(ms_batch), 2), "batched_ms": round(ms_batch, 4),
+            "batched_ids_only_gbps": round(gbps(ms_batch_ids), 2), "batched_ids_only_ms": round(ms_batch_ids, 4),
+            "batched_ids_only": "the same call without per-text counts (no clearing kernel)",
             "graph_gbps": round(gbps(ms_graph), 2), "graph_ms": round(ms_graph, 4),
             "tuned_gbps": round(gbps(ms_tuned), 2), "tuned_ms": round(ms_tuned, 4), "tuned_launch": tuned,
             "plain_gbps": round(gbps(ms_plain), 3), "plain_ms": round(ms_plain, 3),

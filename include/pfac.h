@@ -208,7 +208,8 @@ typedef struct {
  * (the host sizes the launch from it without reading device memory); launch
  * may be NULL (defaults, or the choice ac_tune_batch recorded).  Returns the
  * true total count as ac_match does; per_text_count, if given, receives exact
- * per-text counts (it is cleared by the call).
+ * per-text counts (it is cleared by the call, with one small clearing kernel
+ * before the scan; without it the call launches the scan kernel alone).
  * Errors: AC_EINVAL, AC_ENOTSUP (launch->policy == AC_POLICY_DIRECT), AC_EHIP.
  */
 int64_t ac_match_batch(const ac_automaton *a, const uint8_t *d_texts,

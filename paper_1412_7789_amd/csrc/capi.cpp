@@ -36,8 +36,8 @@ int hip_fail(const char *what, hipError_t e) {
 // allocated on first use and kept until the stream's scratch is released.
 // The synchronous calls never clear the device word: it only grows, the
 // pinned word holds its value after the last such call, and a scan numbers
-// its matches from that value on (ScanArgs::count_base).  The batch calls
-// clear it with their per-text counts.  The filtered policy's hit regions
+// its matches from that value on (ScanArgs::count_base).  A batch call that
+// asks for per-text counts clears it along with them (one clearing kernel).  The filtered policy's hit regions
 // are sized for the widest launch when the slot is created and never change
 // afterwards, so a HIP graph that captured their address stays valid.
 struct CountSlot {
@@ -329,8 +329,9 @@ int64_t sync_count(const ac_automaton *a, ScanArgs S, const ac_launch *launch, b
         T.scan0 = slot->ev[0];
         T.scan1 = slot->ev[1];
     }
-    // a batch clears the word (its per-text counts need a clearing kernel anyway)
-    const bool clear = batch || slot->stale;
+    // a batch with per-text counts clears the word (its counts need a
+    // clearing kernel anyway); any other call numbers on from the word
+    const bool clear = (batch && S.per_text) || slot->stale;
     const unsigned long long base = clear ? 0ull : *slot->h;
     S.count_base = base;
     if (S.n == 0 && !clear) return 0;              // nothing to scan, nothing to clear

@@ -226,6 +226,40 @@ def test_batch_edge_cases():
         assert (per == np.bincount(et, minlength=len(texts))).all()
 
 
+def test_batches_without_per_text_counts_interleave_with_single_calls():
+    """A batch call without per-text counts launches the scan kernel alone
+    and numbers its matches on from the stream's count word, as single-text
+    calls do; one with per-text counts clears the word first.  Interleaved on
+    one stream, every call gives its own exact result."""
+    w = config_batched()
+    n = 500
+    end = int(w.offsets[n])
+    texts, offsets = w.texts[:end], w.offsets[:n + 1]
+    a = pf.Automaton(w.keywords)
+    et, eo, ep = batch_expected(w.keywords, texts, offsets)
+    want = batch_key(et, eo, ep)
+    single = w.texts[end:end + 3 * MIB]
+    exp_single = Oracle(w.keywords).match(single)
+    d_texts = torch.from_numpy(texts).cuda()
+    d_offs = torch.from_numpy(offsets).cuda()
+    cap = len(et) + 64
+    tid = torch.empty(cap, dtype=torch.int32, device="cuda")
+    off = torch.empty(cap, dtype=torch.int64, device="cuda")
+    pid = torch.empty(cap, dtype=torch.int32, device="cuda")
+    per = torch.empty(n, dtype=torch.int64, device="cuda")
+    for step, kind in enumerate(["plain", "single", "plain", "per", "plain", "single", "single", "plain", "per"]):
+        say("interleave", step, kind)
+        if kind == "single":
+            assert_same(run_gpu(a, single), exp_single, f"single text, step {step}")
+            continue
+        got = a.match_batch_into(d_texts, d_offs, tid, off, pid, per if kind == "per" else None)
+        assert got == len(et), (step, kind, got)
+        t, o, p = (x[:got].cpu().numpy() for x in (tid, off, pid))
+        assert (batch_key(t, o, p) == want).all(), (step, kind)
+        if kind == "per":
+            assert (per.cpu().numpy() == np.bincount(et, minlength=n)).all(), step
+
+
 @pytest.mark.parametrize("n_texts", [12000, 16383, 16384, 24000])
 def test_batch_text_lookup_in_lds_and_global(n_texts):
     """Walks find their text by a binary search over the text starts, in LDS
