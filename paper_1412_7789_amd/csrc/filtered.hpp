@@ -27,10 +27,11 @@ constexpr int kDrain = 64;       // candidates taken per drain (1 per lane; 128 
 static_assert(2 * kDrain <= kQueueCap - 4, "queue room");
 constexpr int kMaxWaves = 16;    // waves per block at most (1024 threads)
 // AC_FILTER_PAIR20 is the default (for texts of 16 MiB and more) at stride 4
-// up to this many 4-byte windows, else at stride 2 up to kPair2MaxKeys: two
-// bits per key fill about 2 keys / 2^15 of the map
+// up to this many 4-byte windows (two bits per key), else at stride 2 up to
+// kPair2MaxKeys (three bits per key; measured ahead of the other maps up to
+// 100,000 windows)
 constexpr int32_t kPairMaxKeys = 12000;
-constexpr int32_t kPair2MaxKeys = 32768;
+constexpr int32_t kPair2MaxKeys = 131072;
 // (queue entry, keyword id) pairs a wave's queue holds as its match stage,
 // after its count and before the slot counter
 constexpr int kWaveStageCap = (kQueueCap - 4) / 2;

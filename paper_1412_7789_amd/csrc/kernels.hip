@@ -174,7 +174,13 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         // dual at stride 2; 20000 byte keywords (29958 4-byte windows at
         // stride 2) 0.275 with the 4-byte-window map at stride 2, 0.284 dual
         // at stride 2, 0.437 with the 4-byte-window map at stride 4, 0.567
-        // with one 2^20-bit map at stride 2.
+        // with one 2^20-bit map at stride 2 (the stride-2 map has since
+        // gained its third bit: 0.245).  On 256 MiB of random bytes, 20000
+        // keywords of 8..64 bytes (39999 windows): 0.071 ms with the
+        // 4-byte-window map at stride 2, 0.078 dual at stride 2, 0.099 with
+        // a 2^20-bit map at stride 1; 50000 such keywords (99998 windows):
+        // 0.126 with the 4-byte-window map at stride 2, 0.132 dual at stride
+        // 1, 0.149 dual at stride 2.
         const bool auto_filter = cfg.filter < AC_FILTER_BYTES17 || cfg.filter > AC_FILTER_PAIR20;
         const bool auto_stride = cfg.stride != 1 && cfg.stride != 2 && cfg.stride != 4;
         const bool small_text = len < (int64_t(16) << 20);
@@ -182,7 +188,8 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
             if (auto_filter && !small_text && P.pair4 && P.n_quads4 <= kPairMaxKeys) {
                 cfg.stride = 4;
                 cfg.filter = AC_FILTER_PAIR20;
-            } else if (P.sampled && P.n_windows2 <= 65536) {
+            } else if (P.sampled && (P.n_windows2 <= 65536 ||
+                                     (auto_filter && !small_text && P.pair2 && P.n_quads2 <= kPair2MaxKeys))) {
                 cfg.stride = 2;
                 if (auto_filter && !small_text && P.pair2 && P.n_quads2 <= kPair2MaxKeys) cfg.filter = AC_FILTER_PAIR20;
             } else {
