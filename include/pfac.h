@@ -367,9 +367,13 @@ int ac_probe_read(const uint8_t *d_buf, int64_t n, uint32_t *d_out, hipStream_t 
  *                                          keyword-byte position of the first byte below
  *                                          the state, bytes to the leaf, the leaf's only
  *                                          keyword id + 1 or 0} for a forced path;
- *                                          {-2, 0, 0, 0} at a leaf; {-1, first child,
- *                                          child count, 0} otherwise; bit 31 of the last
- *                                          field set when a keyword ends at the state
+ *                                          {-3, keyword-byte position, bytes to c, c} when
+ *                                          a unary chain of 2+ bytes with no keyword
+ *                                          ending inside leads to a state c that ends a
+ *                                          keyword or branches; {-2, 0, 0, 0} at a leaf;
+ *                                          {-1, first child, child count, 0} otherwise;
+ *                                          bit 31 of the last field set when a keyword
+ *                                          ends at the state
  *   AC_TABLE_FILTER_BASE + k   filter map of kind k = AC_FILTER_* (stride 1),
  *                              k = 6 + AC_FILTER_* (stride 2, may be empty),
  *                              k = 12 + AC_FILTER_* (stride 4, may be empty);

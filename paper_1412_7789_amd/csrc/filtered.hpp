@@ -347,7 +347,9 @@ __device__ __forceinline__ int find_byte16(u32x4 v, int n, uint32_t b) {
 // reads the state's 16-byte walk record (tail info): whether a keyword ends
 // there, and either a forced path (a unary chain to a leaf with no keyword
 // ending in between, whose leaf keyword is then compared with the text
-// directly) or the state's children.  A dense state's next state comes from
+// directly), a unary chain to a deeper state that ends a keyword or
+// branches (compared the same way, then the walk goes on from there), or
+// the state's children.  A dense state's next state comes from
 // its transition row, with the byte's class loaded beside the record; a
 // compact state's children are consecutive states with sorted edge labels,
 // found among up to 16 labels read in one load.  The walk never reads at or
@@ -401,6 +403,15 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, in
             if (only > 0) one(only - 1);
             else ids(ti.x);
             return;
+        }
+        if (ti.x == -3) {
+            // a unary chain of ti.z bytes (no keyword ends inside it) to
+            // state ti.w: compared in one pass, like a forced path
+            if (o + d + ti.z > end) return;
+            if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
+            s = ti.w & 0x7fffffff;
+            d += ti.z;
+            continue;
         }
         if (ti.x == -2 || !has_byte) return;   // a leaf, or the text ends
         if (dense) {

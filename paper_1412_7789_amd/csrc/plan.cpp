@@ -407,17 +407,40 @@ int compile_plan(const uint8_t *bytes, const int64_t *offsets, int32_t n,
             else if (!is_final(c)) P.tail[size_t(s)] = P.tail[size_t(c)];
         }
     }
+    // Unary chains that do not end at a leaf: chain[s] = the first state
+    // below s that ends a keyword or has other than one child, when s has
+    // one child (else -1); rep[s] = a keyword whose path passes through s
+    // down to a leaf (so it spells every chain below s).
+    std::vector<int32_t> chain(size_t(S), -1), rep(size_t(S), -1);
+    for (int32_t s = S - 1; s >= 0; --s) {
+        const int32_t nc = P.n_child[size_t(s)];
+        rep[size_t(s)] = nc > 0 ? rep[size_t(P.first_child[size_t(s)])] : P.out_pid[size_t(P.out_off[size_t(s)])];
+        if (nc == 1) {
+            const int32_t c = P.first_child[size_t(s)];
+            chain[size_t(s)] = (is_final(c) || P.n_child[size_t(c)] != 1) ? c : chain[size_t(c)];
+        }
+    }
     // per state, everything one step of a walk needs in one 16-byte record:
     // {leaf, position in kw_bytes of the first byte below s, bytes from s
     // down to the leaf, leaf's only keyword id + 1 or 0} when tail[s] is a
-    // deeper leaf; {-2, 0, 0, 0} when s is itself a leaf; {-1, first child,
-    // child count, 0} when the path below s is not forced.  Bit 31 of the
-    // last field is set when a keyword ends at s.
+    // deeper leaf; {-3, position in kw_bytes of the first byte below s,
+    // bytes from s down to c, c} when s starts a unary chain of two or more
+    // bytes to a state c that ends a keyword or branches (no state strictly
+    // between ends one); {-2, 0, 0, 0} when s is itself a leaf; {-1, first
+    // child, child count, 0} otherwise.  Bit 31 of the last field is set
+    // when a keyword ends at s.
     P.tailinfo.assign(size_t(S) * 4, 0);
     for (int32_t s = 0; s < S; ++s) {
         const int32_t t = P.tail[size_t(s)];
         int32_t *ti = &P.tailinfo[size_t(s) * 4];
-        if (t < 0) {
+        const int32_t c = chain[size_t(s)];
+        if (t < 0 && c >= 0 && P.depth[size_t(c)] - P.depth[size_t(s)] >= 2) {
+            const int32_t p = rep[size_t(s)];
+            ti[0] = -3;
+            ti[1] = int32_t(offsets[p] - offsets[0]) + P.depth[size_t(s)];
+            ti[2] = P.depth[size_t(c)] - P.depth[size_t(s)];
+            ti[3] = c;
+        } else if (t < 0) {
             ti[0] = -1;
             ti[1] = P.first_child[size_t(s)];
             ti[2] = P.n_child[size_t(s)];

@@ -89,6 +89,7 @@ def kw_sets():
     rng = np.random.default_rng(2)
     yield "fig4", [b"AB", b"ABG", b"BEDE", b"ED"]
     yield "nested", [b"a", b"ab", b"abc", b"bc", b"c", b"abc"]
+    yield "chains", [b"abcdefghij", b"abcdefghXY", b"abcde", b"abcdefghijklmnop", b"zz1", b"zzzzzzzzzzzz2"]
     yield "tiny", make_keywords(SPECS["tiny"], np.random.default_rng(0), np.random.default_rng(1))
     yield "bytes", [bytes(rng.integers(0, 256, size=int(L), dtype=np.uint8)) for L in rng.integers(1, 9, size=300)]
     yield "shared", make_keywords(dataclasses.replace(SPECS["large"], n=500),
@@ -213,10 +214,22 @@ def test_prefix_table_and_tails(name, kws):
         assert (int(ti[3]) < 0) == bool(T.outputs(s)), s
         only = int(ti[3]) & 0x7FFFFFFF
         if leaf is None:
-            # not forced: the children are states ti[1] .. ti[1] + ti[2] - 1
-            ch = sorted(t for t, _ in T.children(s))
-            assert ti[0] == -1 and ch == list(range(int(ti[1]), int(ti[1]) + int(ti[2]))), s
-            assert only == 0
+            # not forced: a unary chain of two or more bytes to a state that
+            # ends a keyword or branches, else the children
+            chain, c = b"", s
+            while len(T.children(c)) == 1:
+                c, fin = T.children(c)[0]
+                chain += bytes([int(T.label[c])])
+                if fin or len(T.children(c)) != 1:
+                    break
+            if len(chain) >= 2:
+                flat = b"".join(kws)
+                assert ti[0] == -3 and only == int(c) and ti[2] == len(chain), s
+                assert flat[ti[1]:ti[1] + ti[2]] == chain, s
+            else:
+                ch = sorted(t for t, _ in T.children(s))
+                assert ti[0] == -1 and ch == list(range(int(ti[1]), int(ti[1]) + int(ti[2]))), s
+                assert only == 0
         elif leaf == s:
             assert ti[0] == -2 and ti[1] == 0 and ti[2] == 0 and only == 0
         else:

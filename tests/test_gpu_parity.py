@@ -318,6 +318,29 @@ def test_long_keywords_and_long_shared_prefixes():
         assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)), exp, f"long {name}")
 
 
+def test_unary_chains_to_final_and_branching_states():
+    """Walk steps that skip a unary chain with one compare: chains that end
+    at a state where a keyword ends, at a branch, or at a forced path;
+    every single-byte change inside each planted keyword; and a text that
+    ends inside a chain."""
+    kws = [b"abcdefghij", b"abcdefghXY", b"abcde", b"abcdefghijklmnop", b"zzzzzzzzzzzz1",
+           b"zzzzzzzzzzzz2", b"qrstuvwxyz0123456789"]
+    text = bytearray()
+    for piece in kws:
+        text += piece + b"."
+        for i in range(len(piece)):
+            changed = bytearray(piece)
+            changed[i] ^= 0x20
+            text += changed + b"."
+    text += b"abcdefghijklm"            # the text ends inside a chain
+    text = bytes(text)
+    exp = oracle_match(kws, text)
+    assert len(exp[0]) >= len(kws)
+    for name, cfg in POLICIES:
+        say("chains", name)
+        assert_same(gpu_match(kws, text, launch=pf.launch_config(**cfg)), exp, f"chains {name}")
+
+
 def test_binary_keywords_with_zero_bytes():
     rng = np.random.default_rng(22)
     kws = [b"\x00\x00\x00\x00", b"\x00\x01\x00", b"\x00" * 9, bytes(range(256)), b"\xff\x00\xff\x00"]
