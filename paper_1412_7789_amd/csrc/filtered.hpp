@@ -355,23 +355,20 @@ __device__ __forceinline__ int find_byte16(u32x4 v, int n, uint32_t b) {
 // found among up to 16 labels read in one load.  The walk never reads at or
 // past `end` (the end of o's text).  With REC, rb holds the 8 text bytes that
 // follow the prefix (as captured by the streaming kernel); the 16 bytes after
-// those (after the prefix without REC) are loaded once at the start, so most
-// walks read no single text bytes.  Every keyword starting at o is reported,
-// through ids(state) for all keyword ids of a final state or one(pid) for a
-// single id.
+// those (after the prefix without REC) are loaded once, when a step first
+// needs one, so most walks read no single text bytes.  Every keyword
+// starting at o is reported, through ids(state) for all keyword ids of a
+// final state or one(pid) for a single id.
 template <bool REC, typename Ids, typename One>
 __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, int64_t o, int64_t end, uint32_t e,
                                           uint2 rb, Ids &&ids, One &&one) {
     const int K = A.K;
     if (o + K > end) return;          // the prefix ran into the next text of a batch
     constexpr int kRec = REC ? 8 : 0;
-    u32x4 more = {0u, 0u, 0u, 0u};    // text bytes o + K + kRec .. + 16
-    if (o + K + kRec < end) {
-        const uint8_t *p = S.text + o + K + kRec;
-        const uintptr_t tend = reinterpret_cast<uintptr_t>(S.text) + uintptr_t(S.n);
-        more = reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p)
-                                                            : load16_clamped(p, (tend - 1u) & ~uintptr_t(3));
-    }
+    // text bytes o + K + kRec .. + 16, loaded the first time a step needs one
+    // (most walks end on a forced path and never do)
+    u32x4 more = {0u, 0u, 0u, 0u};
+    bool have_more = false;
     auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
         int64_t r = j - o - K;
         if (REC) {
@@ -380,6 +377,13 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, in
             r -= 8;
         }
         if (r < 16) {
+            if (!have_more) {
+                const uint8_t *p = S.text + o + K + kRec;
+                const uintptr_t tend = reinterpret_cast<uintptr_t>(S.text) + uintptr_t(S.n);
+                more = reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p)
+                                                                    : load16_clamped(p, (tend - 1u) & ~uintptr_t(3));
+                have_more = true;
+            }
             const uint32_t w = r < 4 ? more.x : r < 8 ? more.y : r < 12 ? more.z : more.w;
             return (w >> (8 * (r & 3))) & 0xFFu;
         }
