@@ -354,9 +354,10 @@ __device__ __forceinline__ int find_byte16(u32x4 v, int n, uint32_t b) {
 // compact state's children are consecutive states with sorted edge labels,
 // found among up to 16 labels read in one load.  The walk never reads at or
 // past `end` (the end of o's text).  With REC, rb holds the 8 text bytes that
-// follow the prefix (as captured by the streaming kernel); the 16 bytes after
-// those (after the prefix without REC) are loaded once, when a step first
-// needs one, so most walks read no single text bytes.  Every keyword
+// follow the prefix (as captured by the streaming kernel), which pick the
+// first transitions without waiting for a load; the 32 bytes after the
+// prefix are loaded at the start, beside the first record, and serve the
+// first compare and the next transitions.  Every keyword
 // starting at o is reported, through ids(state) for all keyword ids of a
 // final state or one(pid) for a single id.
 template <bool REC, typename Ids, typename One>
@@ -364,30 +365,39 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, in
                                           uint2 rb, Ids &&ids, One &&one) {
     const int K = A.K;
     if (o + K > end) return;          // the prefix ran into the next text of a batch
-    constexpr int kRec = REC ? 8 : 0;
-    // text bytes o + K + kRec .. + 16, loaded the first time a step needs one
-    // (most walks end on a forced path and never do)
-    u32x4 more = {0u, 0u, 0u, 0u};
-    bool have_more = false;
+    // The 32 text bytes after the prefix, loaded beside the first walk
+    // record: most walks compare them with a forced path's keyword and read
+    // no other text.
+    const uintptr_t tend = reinterpret_cast<uintptr_t>(S.text) + uintptr_t(S.n);
+    const uintptr_t tlast = (tend - 1u) & ~uintptr_t(3);
+    auto text16 = [&](int64_t j) __attribute__((always_inline)) {   // 16 bytes from text byte j < S.n
+        const uint8_t *p = S.text + j;
+        return reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p) : load16_clamped(p, tlast);
+    };
+    u32x4 t0 = {0u, 0u, 0u, 0u}, t1 = t0;
+    if (o + K < end) {
+        t0 = text16(o + K);
+        if (o + K + 16 < S.n) t1 = text16(o + K + 16);
+    }
     auto byte_at = [&](int64_t j) -> uint32_t {   // text byte j (o + K <= j < end)
-        int64_t r = j - o - K;
-        if (REC) {
-            if (r < 4) return (rb.x >> (8 * r)) & 0xFFu;
-            if (r < 8) return (rb.y >> (8 * (r - 4))) & 0xFFu;
-            r -= 8;
-        }
-        if (r < 16) {
-            if (!have_more) {
-                const uint8_t *p = S.text + o + K + kRec;
-                const uintptr_t tend = reinterpret_cast<uintptr_t>(S.text) + uintptr_t(S.n);
-                more = reinterpret_cast<uintptr_t>(p) + 16u <= tend ? load16_any(p)
-                                                                    : load16_clamped(p, (tend - 1u) & ~uintptr_t(3));
-                have_more = true;
-            }
-            const uint32_t w = r < 4 ? more.x : r < 8 ? more.y : r < 12 ? more.z : more.w;
-            return (w >> (8 * (r & 3))) & 0xFFu;
+        const int64_t r = j - o - K;
+        if (REC && r < 8) return r < 4 ? (rb.x >> (8 * r)) & 0xFFu : (rb.y >> (8 * (r - 4))) & 0xFFu;
+        if (r < 32) {
+            const u32x4 t = r < 16 ? t0 : t1;
+            const int q = int(r & 15);
+            const uint32_t w = q < 4 ? t.x : q < 8 ? t.y : q < 12 ? t.z : t.w;
+            return (w >> (8 * (q & 3))) & 0xFFu;
         }
         return gload1(S.text + j);
+    };
+    // whether text bytes o + dd .. o + dd + z equal keyword bytes kw[0 .. z):
+    // from the preloaded bytes while the walk is still at the prefix
+    auto same = [&](int64_t dd, const uint8_t *kw, int32_t z) -> bool {
+        if (dd == K && z <= 32) {
+            const u32x4 k0 = load16_any(kw), k1 = load16_any(kw + 16);
+            return (diff16(t0, k0, z) | diff16(t1, k1, z - 16)) == 0u;
+        }
+        return equal_bytes(S.text + o + dd, kw, z, S.text, S.n);
     };
     int32_t s = int32_t(e & kStateMask);
     int64_t d = K;
@@ -402,7 +412,7 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, in
             // forced path: bytes d .. d + ti.z of the text against the keyword
             const int64_t L = d + ti.z;
             if (o + L > end) return;
-            if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
+            if (!same(d, A.kw_bytes + ti.y, ti.z)) return;
             const int32_t only = ti.w & 0x7fffffff;
             if (only > 0) one(only - 1);
             else ids(ti.x);
@@ -412,7 +422,7 @@ __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, in
             // a unary chain of ti.z bytes (no keyword ends inside it) to
             // state ti.w: compared in one pass, like a forced path
             if (o + d + ti.z > end) return;
-            if (!equal_bytes(S.text + o + d, A.kw_bytes + ti.y, ti.z, S.text, S.n)) return;
+            if (!same(d, A.kw_bytes + ti.y, ti.z)) return;
             s = ti.w & 0x7fffffff;
             d += ti.z;
             continue;
