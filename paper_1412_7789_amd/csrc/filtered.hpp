@@ -349,17 +349,17 @@ __device__ __forceinline__ int find_byte16(u32x4 v, int n, uint32_t b) {
 // ending in between, whose leaf keyword is then compared with the text
 // directly), a unary chain to a deeper state that ends a keyword or
 // branches (compared the same way, then the walk goes on from there), or
-// the state's children.  A dense state's next state comes from
-// its transition row, with the byte's class loaded beside the record; a
-// compact state's children are consecutive states with sorted edge labels,
-// found among up to 16 labels read in one load.  The walk never reads at or
-// past `end` (the end of o's text).  With REC, rb holds the 8 text bytes that
-// follow the prefix (as captured by the streaming kernel), which pick the
-// first transitions without waiting for a load; the 32 bytes after the
+// the state's children.  A dense state's next state comes from its
+// transition row, with the byte's class loaded beside the record; a compact
+// state's children are consecutive states with sorted edge labels, found
+// among up to 16 labels read in one load.  The walk never compares or steps
+// past `end` (the end of o's text).  With REC, rb holds the 8 text bytes
+// that follow the prefix (as captured by the streaming kernel), which pick
+// the first transitions without waiting for a load; the 32 bytes after the
 // prefix are loaded at the start, beside the first record, and serve the
-// first compare and the next transitions.  Every keyword
-// starting at o is reported, through ids(state) for all keyword ids of a
-// final state or one(pid) for a single id.
+// first compare and the next transitions.  Every keyword starting at o is
+// reported, through ids(state) for all keyword ids of a final state or
+// one(pid) for a single id.
 template <bool REC, typename Ids, typename One>
 __device__ __forceinline__ void walk_rest(const DevAut &A, const ScanArgs &S, int64_t o, int64_t end, uint32_t e,
                                           uint2 rb, Ids &&ids, One &&one) {
