@@ -222,10 +222,20 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         // Texts under 32 MiB take one segment per wave step, which spreads
         // them over more waves (measured on MI355X: a 1 MiB scan in 11 us
         // instead of 19 with four segments).  Above that, two (1 GiB on
-        // MI355X: 1000 keywords, 4-byte-window map at stride 4, 0.213 ms at
-        // two and 0.219 at four; the dual map's four-segment kernel spills
-        // registers).
-        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) cfg.segs = len < (int64_t(32) << 20) ? 1 : 2;
+        // MI355X: 1000 keywords, 4-byte-window map at stride 4, 0.192 ms at
+        // two and 0.200 at four; the dual map's four-segment kernel spills
+        // registers), except for the 4-byte-window map at stride 2 with up
+        // to 65,536 windows on texts of 256 MiB and more, where four halve
+        // the per-step work of a filter-bound loop with few drains (20000
+        // byte keywords, 29974 windows: 1 GiB 0.221 ms at four and 0.241 at
+        // two, 256 MiB 0.070 and 0.075; 20000 keywords of 8..64 bytes, 39999
+        // windows: 1 GiB 0.234 and 0.252; 50000 such keywords, 99998
+        // windows, whose many drains favour two: 0.625 and 0.597).
+        if (cfg.segs != 1 && cfg.segs != 2 && cfg.segs != 4) {
+            cfg.segs = len < (int64_t(32) << 20) ? 1 : 2;
+            if (cfg.filter == AC_FILTER_PAIR20 && cfg.stride == 2 && P.n_quads2 <= 65536 && len >= (int64_t(256) << 20))
+                cfg.segs = 4;
+        }
         const int64_t fit = std::max<int64_t>(1, a->lds_per_cu / filtered_lds(g));
         if (cfg.grid_per_cu <= 0 || cfg.grid_per_cu > fit) cfg.grid_per_cu = int32_t(fit);
     } else {
