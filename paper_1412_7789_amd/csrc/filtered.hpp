@@ -1029,6 +1029,21 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         // barrier the stage and the prefix sums of the counts go where the
         // filter was.
         if (lane == 0) q[0] = uint32_t(hcount);
+        // The text starts go to LDS after the barrier; a batch of up to
+        // kPreTexts starts per thread reads them now, into registers, while
+        // the block's slowest waves still stream.
+        constexpr int kPreTexts = 8;
+        const bool pre_ok = S.n_texts < kPreTexts * int(blockDim.x) && S.n < (int64_t(1) << 32);
+        int64_t pre[kPreTexts];
+        int64_t pre_base = 0;
+        if (pre_ok) {
+            pre_base = S.text_off[0];
+#pragma unroll
+            for (int k = 0; k < kPreTexts; ++k) {
+                const int i = int(threadIdx.x) + k * int(blockDim.x);
+                pre[k] = i <= S.n_texts ? S.text_off[i] : 0;
+            }
+        }
         __syncthreads();
         static_assert((sizeof(MatchStage) + 15) / 16 * 16 + (2 * kMaxWaves + 1) * 4 <= (1u << FLOG2),
                       "the walk's stage must fit where the filter was");
@@ -1049,8 +1064,17 @@ __global__ __launch_bounds__(1024) void filtered_kernel(const KArgs) {
         uint32_t *lds_off = FLOG2 >= 17 ? reinterpret_cast<uint32_t *>(sfilt + kStageEnd) : sptab;
         const uint32_t *loff = nullptr;
         if (total > 0 && S.n_texts < kLdsTexts && S.n < (int64_t(1) << 32)) {
-            const int64_t base0 = S.text_off[0];
-            for (int i = int(threadIdx.x); i <= S.n_texts; i += int(blockDim.x)) lds_off[i] = uint32_t(S.text_off[i] - base0);
+            if (pre_ok) {
+#pragma unroll
+                for (int k = 0; k < kPreTexts; ++k) {
+                    const int i = int(threadIdx.x) + k * int(blockDim.x);
+                    if (i <= S.n_texts) lds_off[i] = uint32_t(pre[k] - pre_base);
+                }
+            } else {
+                const int64_t base0 = S.text_off[0];
+                for (int i = int(threadIdx.x); i <= S.n_texts; i += int(blockDim.x))
+                    lds_off[i] = uint32_t(S.text_off[i] - base0);
+            }
             __syncthreads();
             loff = lds_off;
         }
