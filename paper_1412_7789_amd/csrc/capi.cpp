@@ -37,9 +37,10 @@ int hip_fail(const char *what, hipError_t e) {
 // The synchronous calls never clear the device word: it only grows, the
 // pinned word holds its value after the last such call, and a scan numbers
 // its matches from that value on (ScanArgs::count_base).  A batch call that
-// asks for per-text counts clears it along with them (one clearing kernel).  The filtered policy's hit regions
-// are sized for the widest launch when the slot is created and never change
-// afterwards, so a HIP graph that captured their address stays valid.
+// asks for per-text counts clears it along with them (one clearing kernel).
+// The filtered policy's hit regions are sized for the widest launch when the
+// slot is created and never change afterwards, so a HIP graph that captured
+// their address stays valid.
 struct CountSlot {
     unsigned long long *d = nullptr;           // [0] match count, [1] finished blocks
     unsigned long long *h = nullptr;           // pinned: [0] count, [1] sequence number of the last report

@@ -166,8 +166,9 @@ void resolve_launch(const ac_automaton *a, int64_t len, bool batch, ac_launch &c
         // hold.  A stride of s divides the probes by s but holds s windows per
         // keyword and makes s candidates per positive; the dual map spends a
         // second hash and LDS read per probe to square the false-positive
-        // rate, and the 4-byte-window map (stride 4) sets two bits of one word
-        // per key, which cuts false positives without a second LDS read.
+        // rate, and the 4-byte-window map sets two bits (three at stride 2)
+        // of one word per key, which cuts false positives without a second
+        // LDS read.
         // Measured on MI355X (ms per GiB, two segments): 1000 printable
         // keywords 0.193 with the 4-byte-window map at stride 4, 0.214 with
         // it at stride 2, 0.217 with one 2^20-bit map at stride 2, 0.269
