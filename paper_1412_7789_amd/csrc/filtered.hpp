@@ -494,14 +494,21 @@ struct ChunkRegs {
 // loads from a descriptor based at the chunk (uniform, in SGPRs) with
 // per-lane offsets that never change, so issuing the next chunk's loads
 // needs no address register that an earlier load might still be writing.
+// The loads are non-temporal: the stream passes through the caches without
+// pushing out the tables and records that drains and walks read (1 GiB,
+// 1000 keywords: 0.178 ms instead of 0.191; the 4096-text batch, whose
+// block-wide walk follows the stream closely, 1% slower; a uniform branch
+// that kept the default policy for batches cost more than either).
 template <int SEGS>
 __device__ __forceinline__ void load_interior(const FilterLaunch &F, int64_t c, unsigned lane, ChunkRegs<SEGS> &R) {
     constexpr int64_t CH = int64_t(SEGS) * kSegBytes;
+    constexpr int kNonTemporal = 2;     // cache-policy operand of the buffer loads: nt
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint8_t *>(F.base + c * CH), short(0), int(CH + 16), kBufferFlags);
 #pragma unroll
     for (int j = 0; j < SEGS; ++j) {
-        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(lane * 16u + uint32_t(j) * kSegBytes), 0, 0);
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(rsrc, int(lane * 16u + uint32_t(j) * kSegBytes), 0,
+                                                              kNonTemporal);
         R.d[j][0] = q.x; R.d[j][1] = q.y; R.d[j][2] = q.z; R.d[j][3] = q.w;
     }
     R.tail = __builtin_amdgcn_raw_buffer_load_b32(rsrc, int(CH), 0, 0);
