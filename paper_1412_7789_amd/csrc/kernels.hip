@@ -86,12 +86,13 @@ __global__ void zero_kernel(unsigned long long *count, unsigned long long *done,
 }
 
 // Achievable-bandwidth probe: every lane streams 16-byte words and folds them
-// into one value, written once per wave so the loads cannot be dropped.
+// into one value, written once per wave so the loads cannot be dropped.  The
+// loads are non-temporal, as the scan's stream loads are.
 __global__ __launch_bounds__(256) void probe_read_kernel(const uint8_t *buf, int64_t n16, uint32_t *out) {
     uint32_t acc = 0;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16; i += stride) {
-        const u32x4 v = gload16(buf + i * 16);
+        const u32x4 v = __builtin_nontemporal_load((const global_u32x4 *)(buf + i * 16));
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     for (int d = 32; d >= 1; d >>= 1) acc ^= __shfl_xor(acc, d);
