@@ -114,7 +114,10 @@ def full_oracle(keywords, text):
 def test_sweep_1gib_launch():
     w = config_sweep(GIB)
     a = pf.Automaton(w.keywords)
-    say("sweep 1 GiB", a.default_launch(GIB))
+    launch = a.default_launch(GIB)
+    say("sweep 1 GiB", launch)
+    # the measured default for 1000 printable keywords: 4-byte windows at stride 4, two segments
+    assert (launch["stride"], launch["filter"], launch["segs"]) == (4, 6, 2)
     off, pid = run_gpu(a, w.text)
     off, pid = as_pairs(off, pid)
     assert len(off) > 250_000
@@ -135,7 +138,8 @@ def test_large_automaton_64mib_full():
     assert_same(run_gpu(a, w.text), exp, "large 64 MiB")
     for cfg in [dict(policy=1, filter=1, stride=1), dict(policy=1, filter=4, segs=1, stride=2),
                 dict(policy=1, filter=2, stride=2), dict(policy=1, filter=5, stride=1),
-                dict(policy=1, filter=6, stride=4), dict(policy=1, filter=6, stride=2, segs=2), dict(policy=2)]:
+                dict(policy=1, filter=6, stride=4), dict(policy=1, filter=6, stride=2, segs=2),
+                dict(policy=1, filter=6, stride=2, segs=4), dict(policy=2)]:
         say("large policy", cfg)
         assert_same(run_gpu(a, w.text, pf.launch_config(**cfg)), exp, str(cfg))
 
@@ -143,7 +147,11 @@ def test_large_automaton_64mib_full():
 def test_large_automaton_1gib_launch():
     w = config_large_automaton(GIB)
     a = pf.Automaton(w.keywords)
-    say("large 1 GiB", a.default_launch(GIB))
+    launch = a.default_launch(GIB)
+    say("large 1 GiB", launch)
+    # the measured default for 20000 byte keywords: 4-byte windows (three bits) at stride 2, four segments
+    assert (launch["stride"], launch["filter"], launch["segs"]) == (2, 6, 4)
+    assert a.default_launch(128 * MIB)["segs"] == 2
     off, pid = run_gpu(a, w.text)
     off, pid = as_pairs(off, pid)
     say("large 1 GiB: oracle")
